@@ -1,0 +1,209 @@
+/*
+ * sieve.h -- C ABI of the MI355X segmented wheel sieve (libsieve.so).
+ *
+ * The library counts and lists the primes of half-open integer ranges
+ * [lo, hi) with the incremental segmented Sieve of Eratosthenes over the
+ * 6k+1 / 6k+5 wheel of Ning & Kaeli, "Memory Efficient Multithreaded
+ * Incremental Segmented Sieve Algorithm" (arXiv 2310.17746):
+ *   - only values congruent to 1 or 5 mod 6 are stored, in two arrays A_one
+ *     and A_five (Sec. 2.1, Fig. 2), here bit-packed planes in LDS;
+ *   - the range is cut into contiguous segments, each owned by one worker
+ *     (Sec. 2.2, 2.3), here one workgroup per segment ("tile");
+ *   - each base prime P starts at max(P*P, segment start) (Sec. 1.1, 2.4),
+ *     at the indices given by Table 1 (Sec. 3), and strides by P indices;
+ *   - the survivors are counted, or listed in increasing order (Fig. 1,
+ *     Fig. 4: "return all k such that mod1[k] or mod5[k]").
+ * 2 and 3 lie outside the wheel and are reported when in range; 1 is not
+ * prime and never reported.
+ *
+ * Conventions for every call:
+ *   - Ranges are half-open [lo, hi) with 0 <= lo <= hi <= SIEVE_MAX_HI.
+ *     lo == hi is an empty range; lo > hi is SIEVE_E_INVAL.
+ *   - Sieving [lo, hi) needs every prime <= isqrt(hi - 1) resident on the
+ *     device (sieve_base_primes); otherwise the call returns SIEVE_E_RANGE.
+ *   - Every call returns an int status (SIEVE_OK or a negative code).  No
+ *     C++ exception crosses this ABI.  The last status of a context is kept
+ *     (sieve_last_error).
+ *   - The caller owns every buffer it passes, host or device; the library
+ *     never frees or retains them after the call returns.
+ *   - `stream` arguments take a hipStream_t (for instance
+ *     torch.cuda.current_stream().cuda_stream); NULL selects the context's
+ *     own stream.  Work is ordered after earlier work on that stream, and the
+ *     call returns when its work has finished (host outputs are then valid).
+ *   - A context is not thread-safe, except for the sieve_server_* calls.
+ */
+#ifndef SIEVE_H
+#define SIEVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define SIEVE_OK 0
+#define SIEVE_E_INVAL (-1)     /* bad argument: lo > hi, hi too large, NULL pointer, bad param */
+#define SIEVE_E_RANGE (-2)     /* base primes do not cover isqrt(hi - 1) */
+#define SIEVE_E_CAPACITY (-3)  /* list longer than the output capacity; count still reported */
+#define SIEVE_E_DTYPE (-4)     /* elem_bytes not 4/8, or 4 with hi - 1 > 2^32 - 1 */
+#define SIEVE_E_NOMEM (-5)     /* device or host allocation failed */
+#define SIEVE_E_DEVICE (-6)    /* HIP runtime error, no device, wrong architecture */
+#define SIEVE_E_BUSY (-7)      /* server queue full */
+#define SIEVE_E_CANCELLED (-8) /* request cancelled before it finished */
+
+/* Largest accepted hi (ranges are [lo, hi) with hi <= 2^63). */
+#define SIEVE_MAX_HI ((uint64_t)1 << 63)
+
+typedef struct sieve_ctx sieve_ctx;
+
+/*
+ * Tuning parameters (the paper's inputs t, N, S of Fig. 4 become workgroup
+ * size, range and segment bytes).  Zero in any field selects the default.
+ *   segment_bytes    LDS bytes per tile for the two bit planes together;
+ *                    a multiple of 4096 in [8192, device LDS limit].  A tile
+ *                    covers 24 * segment_bytes consecutive integers.
+ *   block_threads    threads per workgroup: 256, 512 or 1024.
+ *   presieve_groups  number of repeating-pattern groups used to initialise
+ *                    the planes (0..5; 5 covers every prime 5..61).  0 means
+ *                    default; SIEVE_PRESIEVE_NONE disables the presieve.
+ *   split_hits       target hits per marking work item: primes with more
+ *                    hits per tile are split over several lanes.
+ *   bucket_threshold primes at least this large (and larger than a plane)
+ *                    go through the bucket sieve on multi-tile ranges;
+ *                    SIEVE_BUCKET_NEVER disables it.
+ *   wg_per_cu        persistent workgroups launched per compute unit.
+ *   use_graph        1: batched calls replay a captured hipGraph.
+ */
+typedef struct sieve_params {
+    uint32_t segment_bytes;
+    uint32_t block_threads;
+    uint32_t presieve_groups;
+    uint32_t split_hits;
+    uint32_t bucket_threshold;
+    uint32_t wg_per_cu;
+    uint32_t use_graph;
+    uint32_t reserved;
+} sieve_params;
+
+#define SIEVE_PRESIEVE_NONE 0xFFFFFFFFu
+#define SIEVE_BUCKET_NEVER 0xFFFFFFFFu
+
+/* Fills *p with the library defaults for gfx950. */
+int sieve_default_params(sieve_params *p);
+
+/*
+ * Creates a context on HIP device `device` (must be gfx950).  The context
+ * owns the resident base primes (the paper's Sieve Data Store, Sec. 4),
+ * presieve pattern tables, scratch, captured graphs and a stream.
+ * p == NULL selects the defaults.  On success *ctx is set.
+ */
+int sieve_create(sieve_ctx **ctx, int device, const sieve_params *p);
+
+/* Releases every resource of ctx (NULL is accepted). */
+int sieve_destroy(sieve_ctx *ctx);
+
+/* Copies the parameters the context actually uses into *p. */
+int sieve_get_params(const sieve_ctx *ctx, sieve_params *p);
+
+/*
+ * Makes every prime <= limit resident on the device (Sec. 4: only primes up
+ * to the square root are needed for sieving).  Grow-only and idempotent: a
+ * smaller limit than the current one does nothing.  limit < 2^32.  The
+ * primes beyond isqrt(limit) are produced by this library's own GPU list
+ * path.  *n_out (optional) receives the number of resident primes >= 5.
+ */
+int sieve_base_primes(sieve_ctx *ctx, uint64_t limit, uint64_t *n_out);
+
+/* Current base-prime limit (0 when none are resident). */
+int sieve_base_limit(const sieve_ctx *ctx, uint64_t *limit);
+
+/*
+ * Number of primes in [lo, hi) into *count (host).  Synchronous, on the
+ * context stream.
+ */
+int sieve_count(sieve_ctx *ctx, uint64_t lo, uint64_t hi, uint64_t *count);
+
+/*
+ * Writes the primes of [lo, hi) in strictly increasing order to out_dev
+ * (device memory owned by the caller, elem_bytes = 4 for uint32 or 8 for
+ * uint64, little-endian, contiguous).  *n_out (required) receives the count.
+ * If the count exceeds cap, nothing is guaranteed to be written, the call
+ * returns SIEVE_E_CAPACITY and *n_out holds the required count.
+ * elem_bytes = 4 needs hi - 1 <= 2^32 - 1, else SIEVE_E_DTYPE.
+ */
+int sieve_list(sieve_ctx *ctx, uint64_t lo, uint64_t hi, void *out_dev, uint64_t cap,
+               int elem_bytes, uint64_t *n_out, void *stream);
+
+/*
+ * Batched count over n ranges lo[i], hi[i] (host arrays) in one persistent
+ * launch; counts[i] (host) receives the prime count of range i.  Any invalid
+ * range fails the whole call before launch.
+ */
+int sieve_count_batch(sieve_ctx *ctx, const uint64_t *lo, const uint64_t *hi, uint64_t n,
+                      uint64_t *counts, void *stream);
+
+/*
+ * Mixed batch.  For range i (host arrays): mode[i] = 0 counts, 1 also lists
+ * the primes into out_dev at element offset off[i] with capacity cap[i]
+ * (elements of elem_bytes).  counts[i] (host) receives every range's count;
+ * status[i] (host) receives SIEVE_OK or, for a list range that does not fit,
+ * SIEVE_E_CAPACITY (its count is still reported; other ranges are not
+ * affected).  The call returns SIEVE_OK when every range was processed even
+ * if some status[i] is SIEVE_E_CAPACITY.  off/cap may be NULL when no range
+ * lists.  List outputs of different ranges must not overlap.
+ */
+int sieve_list_batch(sieve_ctx *ctx, const uint64_t *lo, const uint64_t *hi,
+                     const uint8_t *mode, uint64_t n, void *out_dev, const uint64_t *off,
+                     const uint64_t *cap, int elem_bytes, uint64_t *counts, int32_t *status,
+                     void *stream);
+
+/*
+ * A rigorous upper bound on the number of primes in [lo, hi), used for
+ * output sizing and admission: the minimum of (values coprime to 6 in the
+ * range + 2) and the Brun-Titchmarsh bound 2y/ln y (y = hi - lo > 1) of
+ * Montgomery and Vaughan (Mathematika 20, 1973), rounded up.
+ */
+uint64_t sieve_list_bound(uint64_t lo, uint64_t hi);
+
+/*
+ * Table 1 (Sec. 3) for one prime, evaluated by the library's own wheel
+ * start-offset code compiled for the host: for a prime p >= 5, a segment
+ * whose index 0 stands for the values base + 1 and base + 5 (base a
+ * multiple of 6) and a first value M >= 1, *id1 and *id5 receive the indices
+ * in A_one / A_five of the first multiple of p that is >= M.  Requires
+ * base <= M < base + 2^40 (M lies in or near the segment) and p < 2^32.
+ * Host-only, no device work.
+ */
+int sieve_wheel_start(uint64_t p, uint64_t base, uint64_t M, int64_t *id1, int64_t *id5);
+
+/*
+ * Tile plan of one range for a given segment size (host-only): *ntiles
+ * receives the number of tiles, *base the value base of tile 0 (a multiple
+ * of 6), *last_words the plane words of the last tile.
+ */
+int sieve_plan_range(uint64_t lo, uint64_t hi, uint32_t segment_bytes, uint64_t *ntiles,
+                     uint64_t *base, uint32_t *last_words);
+
+/*
+ * Event timing of the job phases, for measurement: when on, every
+ * non-graph job records the duration of its sieve kernel and of its
+ * finalize + compaction kernels (HIP events on the stream the kernels run
+ * on).  sieve_get_timing returns the sums in milliseconds and the number of
+ * jobs timed; sieve_set_timing resets them.
+ */
+int sieve_set_timing(sieve_ctx *ctx, int on);
+int sieve_get_timing(const sieve_ctx *ctx, double *sieve_ms, double *post_ms, uint64_t *jobs);
+
+/* Text for a status code (static storage). */
+const char *sieve_strerror(int status);
+
+/* Last status returned by a call on ctx. */
+int sieve_last_error(const sieve_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIEVE_H */

@@ -1,0 +1,287 @@
+"""MI355X segmented wheel sieve: Python binding of libsieve.so.
+
+Argument marshalling only: every step of the sieve runs in the library's HIP
+kernels.  PyTorch supplies device memory for list outputs and the HIP stream
+they are ordered on.  Importing this package does not load the library; the
+first use does, and it raises if ``libsieve.so`` was not built (there is no
+fallback path).
+
+    from paper_2310_17746_amd import Sieve
+    s = Sieve()                      # device 0, default parameters
+    s.base_primes(10**6)             # resident primes <= 10^6
+    s.count(2, 10**12 + 1)           # pi(10^12)
+    t = s.list(10**9, 10**9 + 10**6) # torch tensor of uint64 primes on cuda
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = ["Sieve", "SieveError", "Params", "list_bound", "wheel_start", "plan_range",
+           "lib_path", "load_library", "SIEVE_OK", "SIEVE_E_CAPACITY"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libsieve.so")
+_lib = None
+
+SIEVE_OK = 0
+SIEVE_E_INVAL = -1
+SIEVE_E_RANGE = -2
+SIEVE_E_CAPACITY = -3
+SIEVE_E_DTYPE = -4
+SIEVE_E_NOMEM = -5
+SIEVE_E_DEVICE = -6
+SIEVE_E_BUSY = -7
+SIEVE_E_CANCELLED = -8
+PRESIEVE_NONE = 0xFFFFFFFF
+BUCKET_NEVER = 0xFFFFFFFF
+
+_u64 = ctypes.c_uint64
+_p = ctypes.c_void_p
+
+
+class Params(ctypes.Structure):
+    """sieve_params (include/sieve.h); zero fields select the defaults."""
+    _fields_ = [("segment_bytes", ctypes.c_uint32), ("block_threads", ctypes.c_uint32),
+                ("presieve_groups", ctypes.c_uint32), ("split_hits", ctypes.c_uint32),
+                ("bucket_threshold", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32),
+                ("use_graph", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class SieveError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__("%s: %s (%d)" % (what, load_library().sieve_strerror(code).decode(), code))
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Loads libsieve.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError("libsieve.so not built: run __graft_entry__.build() "
+                          "(python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(_LIB_PATH)
+    sig = {
+        "sieve_default_params": (ctypes.c_int, [ctypes.POINTER(Params)]),
+        "sieve_create": (ctypes.c_int, [ctypes.POINTER(_p), ctypes.c_int, ctypes.POINTER(Params)]),
+        "sieve_destroy": (ctypes.c_int, [_p]),
+        "sieve_get_params": (ctypes.c_int, [_p, ctypes.POINTER(Params)]),
+        "sieve_base_primes": (ctypes.c_int, [_p, _u64, ctypes.POINTER(_u64)]),
+        "sieve_base_limit": (ctypes.c_int, [_p, ctypes.POINTER(_u64)]),
+        "sieve_count": (ctypes.c_int, [_p, _u64, _u64, ctypes.POINTER(_u64)]),
+        "sieve_list": (ctypes.c_int, [_p, _u64, _u64, _p, _u64, ctypes.c_int,
+                                      ctypes.POINTER(_u64), _p]),
+        "sieve_count_batch": (ctypes.c_int, [_p, _p, _p, _u64, _p, _p]),
+        "sieve_list_batch": (ctypes.c_int, [_p, _p, _p, _p, _u64, _p, _p, _p, ctypes.c_int,
+                                            _p, _p, _p]),
+        "sieve_list_bound": (_u64, [_u64, _u64]),
+        "sieve_wheel_start": (ctypes.c_int, [_u64, _u64, _u64, ctypes.POINTER(ctypes.c_int64),
+                                             ctypes.POINTER(ctypes.c_int64)]),
+        "sieve_plan_range": (ctypes.c_int, [_u64, _u64, ctypes.c_uint32, ctypes.POINTER(_u64),
+                                            ctypes.POINTER(_u64), ctypes.POINTER(ctypes.c_uint32)]),
+        "sieve_set_timing": (ctypes.c_int, [_p, ctypes.c_int]),
+        "sieve_get_timing": (ctypes.c_int, [_p, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_u64)]),
+        "sieve_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "sieve_last_error": (ctypes.c_int, [_p]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code: int, what: str) -> None:
+    if code != SIEVE_OK:
+        raise SieveError(code, what)
+
+
+def list_bound(lo: int, hi: int) -> int:
+    """Rigorous upper bound on the number of primes in [lo, hi)."""
+    return int(load_library().sieve_list_bound(lo, hi))
+
+
+def wheel_start(p: int, base: int, M: int) -> tuple[int, int]:
+    """Table 1 start indices (id_1, id_5) from the library's host-compiled code."""
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    _check(load_library().sieve_wheel_start(p, base, M, ctypes.byref(a), ctypes.byref(b)),
+           "sieve_wheel_start")
+    return a.value, b.value
+
+
+def plan_range(lo: int, hi: int, segment_bytes: int) -> tuple[int, int, int]:
+    """(ntiles, base, last_words) of the tile plan of [lo, hi)."""
+    n, b, w = _u64(), _u64(), ctypes.c_uint32()
+    _check(load_library().sieve_plan_range(lo, hi, segment_bytes, ctypes.byref(n), ctypes.byref(b),
+                                           ctypes.byref(w)), "sieve_plan_range")
+    return n.value, b.value, w.value
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_for(elem_bytes: int):
+    torch = _torch()
+    return torch.int32 if elem_bytes == 4 else torch.int64
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class Sieve:
+    """A sieve context on one GPU (resident base primes, scratch, stream)."""
+
+    def __init__(self, device: int = 0, params: Params | dict | None = None):
+        lib = load_library()
+        self._lib = lib
+        self.device = device
+        p = None
+        if params is not None:
+            if isinstance(params, dict):
+                q = Params()
+                for k, v in params.items():
+                    setattr(q, k, v)
+                params = q
+            p = ctypes.byref(params)
+        h = _p()
+        _check(lib.sieve_create(ctypes.byref(h), device, p), "sieve_create")
+        self._h = h
+
+    # -- lifetime ----------------------------------------------------------
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.sieve_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- queries -----------------------------------------------------------
+    @property
+    def params(self) -> Params:
+        q = Params()
+        _check(self._lib.sieve_get_params(self._h, ctypes.byref(q)), "sieve_get_params")
+        return q
+
+    @property
+    def base_limit(self) -> int:
+        v = _u64()
+        _check(self._lib.sieve_base_limit(self._h, ctypes.byref(v)), "sieve_base_limit")
+        return v.value
+
+    def base_primes(self, limit: int) -> int:
+        """Makes all primes <= limit resident; returns how many (>= 5) are."""
+        n = _u64()
+        _check(self._lib.sieve_base_primes(self._h, limit, ctypes.byref(n)), "sieve_base_primes")
+        return n.value
+
+    def ensure_base_for(self, hi: int) -> None:
+        """Makes the base primes cover isqrt(hi - 1)."""
+        import math
+        need = math.isqrt(max(hi - 1, 0))
+        if need > self.base_limit:
+            self.base_primes(need)
+
+    def count(self, lo: int, hi: int) -> int:
+        c = _u64()
+        _check(self._lib.sieve_count(self._h, lo, hi, ctypes.byref(c)), "sieve_count")
+        return c.value
+
+    def list(self, lo: int, hi: int, out=None, elem_bytes: int | None = None, stream=None):
+        """Primes of [lo, hi) as a torch tensor on the context's GPU.
+
+        The tensor has dtype int32 (elem_bytes=4) or int64 holding the
+        unsigned values bit for bit.  With `out` given, the primes are
+        written into it and a view of the filled prefix is returned.
+        """
+        torch = _torch()
+        if elem_bytes is None:
+            elem_bytes = 4 if hi <= 2 ** 32 else 8
+        if out is None:
+            out = torch.empty(max(list_bound(lo, hi), 1), dtype=_dtype_for(elem_bytes),
+                              device="cuda:%d" % self.device)
+        if out.element_size() != elem_bytes or not out.is_contiguous():
+            raise ValueError("out must be contiguous with %d-byte elements" % elem_bytes)
+        n = _u64()
+        code = self._lib.sieve_list(self._h, lo, hi, out.data_ptr(), out.numel(), elem_bytes,
+                                    ctypes.byref(n), _stream_handle(stream))
+        if code == SIEVE_E_CAPACITY:
+            raise SieveError(code, "sieve_list needs %d elements" % n.value)
+        _check(code, "sieve_list")
+        return out[: n.value]
+
+    def count_list(self, lo: int, hi: int, elem_bytes: int = 8) -> int:
+        """Count through the list path without an output buffer (cap 0)."""
+        n = _u64()
+        code = self._lib.sieve_list(self._h, lo, hi, None, 0, elem_bytes, ctypes.byref(n), None)
+        if code not in (SIEVE_OK, SIEVE_E_CAPACITY):
+            _check(code, "sieve_list")
+        return n.value
+
+    def count_batch(self, lo, hi, stream=None) -> np.ndarray:
+        lo = np.ascontiguousarray(lo, dtype=np.uint64)
+        hi = np.ascontiguousarray(hi, dtype=np.uint64)
+        if lo.shape != hi.shape:
+            raise ValueError("lo and hi differ in shape")
+        counts = np.zeros(lo.shape, dtype=np.uint64)
+        _check(self._lib.sieve_count_batch(self._h, lo.ctypes.data, hi.ctypes.data, lo.size,
+                                           counts.ctypes.data, _stream_handle(stream)),
+               "sieve_count_batch")
+        return counts
+
+    def list_batch(self, lo, hi, mode, out, off, cap, elem_bytes: int = 8, stream=None):
+        """Mixed batch; returns (counts, status) as numpy arrays."""
+        lo = np.ascontiguousarray(lo, dtype=np.uint64)
+        hi = np.ascontiguousarray(hi, dtype=np.uint64)
+        mode = np.ascontiguousarray(mode, dtype=np.uint8)
+        off = np.ascontiguousarray(off, dtype=np.uint64)
+        cap = np.ascontiguousarray(cap, dtype=np.uint64)
+        n = lo.size
+        counts = np.zeros(n, dtype=np.uint64)
+        status = np.zeros(n, dtype=np.int32)
+        optr = out.data_ptr() if out is not None else None
+        _check(self._lib.sieve_list_batch(self._h, lo.ctypes.data, hi.ctypes.data, mode.ctypes.data,
+                                          n, optr, off.ctypes.data, cap.ctypes.data, elem_bytes,
+                                          counts.ctypes.data, status.ctypes.data,
+                                          _stream_handle(stream)), "sieve_list_batch")
+        return counts, status
+
+    # -- measurement -------------------------------------------------------
+    def set_timing(self, on: bool = True) -> None:
+        _check(self._lib.sieve_set_timing(self._h, 1 if on else 0), "sieve_set_timing")
+
+    def timing(self) -> tuple[float, float, int]:
+        """(sieve kernel ms, finalize+compaction ms, jobs) summed since set_timing."""
+        a, b, n = ctypes.c_double(), ctypes.c_double(), _u64()
+        _check(self._lib.sieve_get_timing(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)),
+               "sieve_get_timing")
+        return a.value, b.value, n.value

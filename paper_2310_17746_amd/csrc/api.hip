@@ -1,0 +1,993 @@
+// Host runtime and C ABI of libsieve (declared in include/sieve.h).
+//
+// Owns the context: the resident base primes (the paper's Sieve Data Store,
+// Sec. 4) with their per-prime constants, the presieve pattern tables, the
+// marking work items, grow-only device scratch, pinned staging, a stream and
+// a captured graph.  Every count / list / batch call is planned here (ranges
+// cut into tiles of 192 * PW integers, Sec. 2.2) and executed as one job:
+// zero -> sieve (persistent) -> finalize -> compact.
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "../../include/sieve.h"
+#include "sieve_internal.h"
+#include "wheel.h"
+
+namespace sieve {
+hipError_t set_sieve_lds_limit(uint32_t bytes);
+hipError_t launch_zero(const JobHeader *job, unsigned long long *counters, unsigned long long *counts,
+                       hipStream_t s);
+hipError_t launch_sieve(const SieveArgs &a, uint32_t nt, uint32_t grid, hipStream_t s);
+hipError_t launch_finalize(const FinalizeArgs &a, uint32_t grid, hipStream_t s);
+hipError_t launch_compact(const CompactArgs &a, uint32_t grid, hipStream_t s);
+}  // namespace sieve
+
+using namespace sieve;
+
+namespace {
+
+// Presieve groups: consecutive primes whose product stays below 2^18 bits.
+const uint32_t kGroupPrimes[kMaxGroups][4] = {
+    {5, 7, 11, 13}, {17, 19, 23, 0}, {29, 31, 37, 0}, {41, 43, 47, 0}, {53, 59, 61, 0}};
+
+constexpr uint32_t kFinalizeGrid = 256;
+
+uint64_t isqrt_host(uint64_t n)
+{
+    if (n < 2)
+        return n;
+    uint64_t x = (uint64_t)std::sqrt((double)n);
+    while (x > n / x)
+        --x;
+    while (x + 1 <= n / (x + 1))
+        ++x;
+    return x;
+}
+
+// Primes 5..limit by a host Eratosthenes (Fig. 1).  Used only to bootstrap
+// the device list path with the primes up to isqrt(limit).
+std::vector<uint32_t> host_small_primes(uint64_t limit)
+{
+    std::vector<uint32_t> out;
+    if (limit < 5)
+        return out;
+    std::vector<uint8_t> a(limit + 1, 1);
+    for (uint64_t i = 2; i * i <= limit; ++i)
+        if (a[i])
+            for (uint64_t j = i * i; j <= limit; j += i)
+                a[j] = 0;
+    for (uint64_t i = 5; i <= limit; ++i)
+        if (a[i])
+            out.push_back((uint32_t)i);
+    return out;
+}
+
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    // Grows to at least `need` elements (contents are not kept).
+    bool reserve(size_t need, uint64_t *gen = nullptr)
+    {
+        if (need <= n && p)
+            return true;
+        size_t m = std::max<size_t>(need, 1);
+        if (p)
+            m = std::max(m, n + n / 2);
+        if (p)
+            (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+        if (gen)
+            ++*gen;
+        T *q = nullptr;
+        if (hipMalloc((void **)&q, m * sizeof(T)) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        p = q;
+        n = m;
+        return true;
+    }
+    void release()
+    {
+        if (p)
+            (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+}  // namespace
+
+struct sieve_ctx {
+    int device = 0;
+    int cus = 0;
+    uint32_t lds_max = 0;
+    sieve_params prm{};
+    hipStream_t stream = nullptr;
+    int last_error = SIEVE_OK;
+
+    // Resident base primes (>= 5) and derived constants.
+    uint64_t limit = 0;
+    std::vector<uint32_t> h_primes;
+    DevBuf<uint2> d_prm;
+    DevBuf<uint64_t> d_rcp;
+    DevBuf<uint32_t> d_pidx;
+    DevBuf<uint2> d_items;
+    DevBuf<uint32_t> d_item_prefix;
+    uint32_t first_mark = 0, k_split = 0;
+
+    // Presieve tables.
+    DevBuf<uint2> d_pstab;
+    PsGroup groups[kMaxGroups]{};
+    uint32_t ngroups = 0;
+    uint32_t restore1 = 0, restore5 = 0;
+
+    // Job scratch.
+    DevBuf<unsigned char> d_blob;  // JobHeader | RangeDesc[] | list_idx[] | list_chunk0[]
+    DevBuf<unsigned long long> d_counters;
+    DevBuf<unsigned long long> d_counts;
+    DevBuf<int32_t> d_status;
+    DevBuf<unsigned long long> d_bitmap;
+    DevBuf<uint32_t> d_chunk_counts;
+    DevBuf<unsigned long long> d_chunk_off;
+    unsigned char *h_blob = nullptr;  // pinned staging for the blob
+    size_t h_blob_n = 0;
+    unsigned long long *h_counts = nullptr;  // pinned
+    int32_t *h_status = nullptr;             // pinned
+    uint64_t cap_ranges = 0, cap_list = 0, cap_chunks = 0;
+
+    // Graph of the job kernels; valid while gen == graph_gen.
+    hipGraphExec_t graph = nullptr;
+    hipGraph_t graph_src = nullptr;
+    uint64_t graph_gen = ~0ull;
+    uint64_t gen = 0;
+
+    // Optional event timing of the sieve kernel and the post-processing.
+    int timing = 0;
+    hipEvent_t ev[3]{};
+    double t_sieve_ms = 0, t_post_ms = 0;
+    uint64_t t_jobs = 0;
+};
+
+namespace {
+
+int set_err(sieve_ctx *c, int e)
+{
+    if (c)
+        c->last_error = e;
+    return e;
+}
+
+int hip_status(hipError_t e)
+{
+    if (e == hipSuccess)
+        return SIEVE_OK;
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? SIEVE_E_NOMEM : SIEVE_E_DEVICE;
+}
+
+void fill_defaults(sieve_params &p)
+{
+    if (!p.segment_bytes)
+        p.segment_bytes = 64 * 1024;
+    if (!p.block_threads)
+        p.block_threads = 512;
+    if (!p.presieve_groups)
+        p.presieve_groups = kMaxGroups;
+    if (!p.split_hits)
+        p.split_hits = 256;
+    if (!p.bucket_threshold)
+        p.bucket_threshold = SIEVE_BUCKET_NEVER;
+    if (!p.wg_per_cu)
+        p.wg_per_cu = std::max<uint32_t>(1, std::min<uint32_t>(4, (160 * 1024) / p.segment_bytes));
+}
+
+int validate_params(const sieve_params &p, uint32_t lds_max)
+{
+    if (p.segment_bytes < 8192 || p.segment_bytes % 4096 || p.segment_bytes > lds_max ||
+        p.segment_bytes > 256 * 1024)
+        return SIEVE_E_INVAL;
+    if (p.block_threads != 256 && p.block_threads != 512 && p.block_threads != 1024)
+        return SIEVE_E_INVAL;
+    if (p.presieve_groups > kMaxGroups && p.presieve_groups != SIEVE_PRESIEVE_NONE)
+        return SIEVE_E_INVAL;
+    if (p.split_hits < 8)
+        return SIEVE_E_INVAL;
+    if (p.wg_per_cu < 1 || p.wg_per_cu > 16)
+        return SIEVE_E_INVAL;
+    return SIEVE_OK;
+}
+
+// Builds the presieve tables for the first `ng` groups and uploads them.
+int build_presieve(sieve_ctx *c, uint32_t ng)
+{
+    std::vector<uint2> tab;
+    c->ngroups = ng;
+    c->restore1 = c->restore5 = 0;
+    for (uint32_t g = 0; g < ng; ++g) {
+        uint32_t P = 1;
+        for (int i = 0; i < 4 && kGroupPrimes[g][i]; ++i)
+            P *= kGroupPrimes[g][i];
+        const uint32_t nw = (P + 64 + 31) / 32 + 1;
+        PsGroup &G = c->groups[g];
+        G.period = P;
+        G.offset = (uint32_t)tab.size();
+        G.step = (32u * c->prm.block_threads) % P;
+        tab.resize(tab.size() + nw, make_uint2(0, 0));
+        for (uint32_t t = 0; t < nw * 32; ++t) {
+            const uint64_t tt = t % P;
+            const uint64_t v1 = 6 * tt + 1, v5 = 6 * tt + 5;
+            bool c1 = false, c5 = false;
+            for (int i = 0; i < 4 && kGroupPrimes[g][i]; ++i) {
+                c1 |= v1 % kGroupPrimes[g][i] == 0;
+                c5 |= v5 % kGroupPrimes[g][i] == 0;
+            }
+            if (c1)
+                tab[G.offset + t / 32].x |= 1u << (t % 32);
+            if (c5)
+                tab[G.offset + t / 32].y |= 1u << (t % 32);
+        }
+        for (int i = 0; i < 4 && kGroupPrimes[g][i]; ++i) {
+            const uint32_t p = kGroupPrimes[g][i];
+            if (p % 6 == 1)
+                c->restore1 |= 1u << ((p - 1) / 6);
+            else
+                c->restore5 |= 1u << ((p - 5) / 6);
+        }
+    }
+    if (tab.empty())
+        tab.push_back(make_uint2(0, 0));
+    if (!c->d_pstab.reserve(tab.size()))
+        return SIEVE_E_NOMEM;
+    return hip_status(hipMemcpy(c->d_pstab.p, tab.data(), tab.size() * sizeof(uint2), hipMemcpyHostToDevice));
+}
+
+// Installs c->h_primes as the resident base primes: per-prime constants, the
+// pi index and the marking work items.
+int install_primes(sieve_ctx *c, uint64_t limit)
+{
+    const std::vector<uint32_t> &P = c->h_primes;
+    const size_t n = P.size();
+    std::vector<uint2> prm(std::max<size_t>(n, 1), make_uint2(0, 0));
+    std::vector<uint64_t> rcp(std::max<size_t>(n, 1), 0);
+    for (size_t k = 0; k < n; ++k) {
+        prm[k] = make_uint2(P[k], P[k] / 6);
+        rcp[k] = UINT64_MAX / P[k];
+    }
+    const size_t np = limit / 64 + 2;
+    std::vector<uint32_t> pidx(np);
+    size_t k = 0;
+    for (size_t s = 0; s < np; ++s) {
+        while (k < n && P[k] <= 64 * s)
+            ++k;
+        pidx[s] = (uint32_t)k;
+    }
+    // Presieved primes are never marked in LDS.
+    uint32_t maxps = 0;
+    for (uint32_t g = 0; g < c->ngroups; ++g)
+        for (int i = 0; i < 4 && kGroupPrimes[g][i]; ++i)
+            maxps = std::max(maxps, kGroupPrimes[g][i]);
+    uint32_t fm = 0;
+    while (fm < n && P[fm] <= maxps)
+        ++fm;
+    // Work items: a prime with more than split_hits hits per plane per tile
+    // is split over g lanes; lane j takes hits j, j + g, j + 2g, ...
+    const uint64_t plane_bits = (uint64_t)(c->prm.segment_bytes / 8) * 32;
+    std::vector<uint2> items;
+    std::vector<uint32_t> prefix(1, 0);
+    uint32_t ks = fm;
+    while (ks < n) {
+        uint64_t g = plane_bits / ((uint64_t)P[ks] * c->prm.split_hits);
+        if (g <= 1)
+            break;
+        g = std::min<uint64_t>(g, 0xFFFF);
+        for (uint32_t j = 0; j < g; ++j)
+            items.push_back(make_uint2(ks, (j << 16) | (uint32_t)g));
+        prefix.push_back((uint32_t)items.size());
+        ++ks;
+    }
+    if (items.empty())
+        items.push_back(make_uint2(0, 0));
+    if (!c->d_prm.reserve(prm.size(), &c->gen) || !c->d_rcp.reserve(rcp.size(), &c->gen) ||
+        !c->d_pidx.reserve(pidx.size(), &c->gen) || !c->d_items.reserve(items.size(), &c->gen) ||
+        !c->d_item_prefix.reserve(prefix.size(), &c->gen))
+        return SIEVE_E_NOMEM;
+    hipError_t e = hipMemcpy(c->d_prm.p, prm.data(), prm.size() * sizeof(uint2), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(c->d_rcp.p, rcp.data(), rcp.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(c->d_pidx.p, pidx.data(), pidx.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(c->d_items.p, items.data(), items.size() * sizeof(uint2), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(c->d_item_prefix.p, prefix.data(), prefix.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess)
+        return hip_status(e);
+    c->limit = limit;
+    c->first_mark = fm;
+    c->k_split = ks;
+    c->gen++;  // kernel arguments changed: a captured graph is stale
+    return SIEVE_OK;
+}
+
+// Tile plan of [lo, hi): tile 0 starts at base = lo - lo % 6; the plane-1
+// index count decides the words (plane 5 never has more indices).
+void plan_range(uint64_t lo, uint64_t hi, uint32_t pw, uint64_t &ntiles, uint64_t &base, uint32_t &last_words)
+{
+    base = lo - lo % 6;
+    ntiles = 0;
+    last_words = 0;
+    if (hi <= base + 1)
+        return;
+    const uint64_t n1 = (hi - base - 1 + 5) / 6;
+    const uint64_t words = (n1 + 31) / 32;
+    ntiles = (words + pw - 1) / pw;
+    last_words = (uint32_t)(words - (ntiles - 1) * pw);
+}
+
+struct Plan {
+    std::vector<RangeDesc> ranges;
+    std::vector<uint32_t> list_idx;
+    std::vector<uint64_t> list_chunk0;
+    uint64_t ntiles = 0, nchunks = 0;
+};
+
+int make_plan(const sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, const uint8_t *mode,
+              const uint64_t *off, const uint64_t *cap, int elem_bytes, Plan &pl)
+{
+    const uint32_t pw = c->prm.segment_bytes / 8;
+    pl.ranges.resize(n);
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint64_t a = lo[i], b = hi[i];
+        if (a > b || b > SIEVE_MAX_HI)
+            return SIEVE_E_INVAL;
+        if (b > 4 && isqrt_host(b - 1) > c->limit)
+            return SIEVE_E_RANGE;
+        const bool lst = mode && mode[i];
+        if (lst && elem_bytes == 4 && b > a && b - 1 > 0xFFFFFFFFull)
+            return SIEVE_E_DTYPE;
+        RangeDesc &d = pl.ranges[i];
+        memset(&d, 0, sizeof d);
+        d.lo = a;
+        d.hi = b;
+        uint64_t nt;
+        plan_range(a, b, pw, nt, d.base, d.last_words);
+        if (nt > 0xFFFFFFFFull)
+            return SIEVE_E_INVAL;
+        d.ntiles = (uint32_t)nt;
+        d.tile0 = pl.ntiles;
+        pl.ntiles += nt;
+        d.mode = lst ? 1u : 0u;
+        if (lst) {
+            d.out_off = off ? off[i] : 0;
+            d.cap = cap ? cap[i] : 0;
+            const uint64_t nch =
+                nt ? (nt - 1) * (pw / kChunkWords) + (d.last_words + kChunkWords - 1) / kChunkWords : 0;
+            if (nch > 0xFFFFFFFFull)
+                return SIEVE_E_INVAL;
+            d.nchunks = (uint32_t)nch;
+            d.chunk0 = pl.nchunks;
+            pl.nchunks += nch;
+            pl.list_idx.push_back((uint32_t)i);
+            pl.list_chunk0.push_back(d.chunk0);
+        }
+    }
+    return SIEVE_OK;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct BlobLayout {
+    size_t ranges, list_idx, list_chunk0, total;
+};
+
+BlobLayout blob_layout(uint64_t nranges, uint64_t nlist)
+{
+    BlobLayout L;
+    L.ranges = align_up(sizeof(JobHeader), 256);
+    L.list_idx = align_up(L.ranges + sizeof(RangeDesc) * std::max<uint64_t>(nranges, 1), 256);
+    L.list_chunk0 = align_up(L.list_idx + sizeof(uint32_t) * std::max<uint64_t>(nlist, 1), 256);
+    L.total = align_up(L.list_chunk0 + sizeof(uint64_t) * std::max<uint64_t>(nlist, 1), 256);
+    return L;
+}
+
+uint64_t grow(uint64_t cur, uint64_t need, uint64_t floor_)
+{
+    if (need <= cur)
+        return cur;
+    return std::max(std::max(need, floor_), cur + cur / 2);
+}
+
+// Makes the scratch hold a job of the given size.  Capacities only grow; any
+// reallocation bumps c->gen so that a captured graph is re-made.
+int ensure_capacity(sieve_ctx *c, uint64_t nranges, uint64_t nlist, uint64_t nchunks)
+{
+    bool changed = false;
+    if (nranges > c->cap_ranges || nlist > c->cap_list || !c->d_blob.p) {
+        c->cap_ranges = grow(c->cap_ranges, nranges, 64);
+        c->cap_list = grow(c->cap_list, nlist, 64);
+        const BlobLayout L = blob_layout(c->cap_ranges, c->cap_list);
+        c->d_blob.release();
+        c->d_counts.release();
+        c->d_status.release();
+        if (!c->d_blob.reserve(L.total) || !c->d_counts.reserve(c->cap_ranges) ||
+            !c->d_status.reserve(c->cap_ranges))
+            return SIEVE_E_NOMEM;
+        if (c->h_blob)
+            (void)hipHostFree(c->h_blob);
+        if (c->h_counts)
+            (void)hipHostFree(c->h_counts);
+        if (c->h_status)
+            (void)hipHostFree(c->h_status);
+        c->h_blob = nullptr;
+        c->h_counts = nullptr;
+        c->h_status = nullptr;
+        if (hipHostMalloc((void **)&c->h_blob, L.total, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&c->h_counts, c->cap_ranges * sizeof(unsigned long long),
+                          hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&c->h_status, c->cap_ranges * sizeof(int32_t), hipHostMallocDefault) !=
+                hipSuccess) {
+            (void)hipGetLastError();
+            return SIEVE_E_NOMEM;
+        }
+        c->h_blob_n = L.total;
+        changed = true;
+    }
+    if (nchunks > c->cap_chunks || !c->d_bitmap.p) {
+        c->cap_chunks = grow(c->cap_chunks, nchunks, 64);
+        c->d_bitmap.release();
+        c->d_chunk_counts.release();
+        c->d_chunk_off.release();
+        if (!c->d_bitmap.reserve(c->cap_chunks * kChunkWords) || !c->d_chunk_counts.reserve(c->cap_chunks) ||
+            !c->d_chunk_off.reserve(c->cap_chunks))
+            return SIEVE_E_NOMEM;
+        changed = true;
+    }
+    if (!c->d_counters.p) {
+        if (!c->d_counters.reserve(kNumCounters))
+            return SIEVE_E_NOMEM;
+        changed = true;
+    }
+    if (changed)
+        c->gen++;
+    return SIEVE_OK;
+}
+
+// Enqueues the job kernels on stream s; also used under graph capture.  All
+// job-specific values are read by the kernels from the device blob, whose
+// layout depends only on the capacities.
+hipError_t enqueue_kernels(sieve_ctx *c, hipStream_t s, bool timed)
+{
+    const BlobLayout L = blob_layout(c->cap_ranges, c->cap_list);
+    const JobHeader *job = (const JobHeader *)c->d_blob.p;
+    const RangeDesc *ranges = (const RangeDesc *)(c->d_blob.p + L.ranges);
+    hipError_t e = launch_zero(job, c->d_counters.p, c->d_counts.p, s);
+    if (e != hipSuccess)
+        return e;
+    SieveArgs a;
+    memset(&a, 0, sizeof a);
+    a.job = job;
+    a.ranges = ranges;
+    a.counters = c->d_counters.p;
+    a.counts = c->d_counts.p;
+    a.prm = c->d_prm.p;
+    a.rcp = c->d_rcp.p;
+    a.pidx = c->d_pidx.p;
+    a.pidx_len = (uint32_t)(c->limit / 64 + 2);
+    a.nprimes = (uint32_t)c->h_primes.size();
+    a.first_mark = c->first_mark;
+    a.k_split = c->k_split;
+    a.items = c->d_items.p;
+    a.item_prefix = c->d_item_prefix.p;
+    a.ps_tab = c->d_pstab.p;
+    for (int g = 0; g < kMaxGroups; ++g)
+        a.groups[g] = c->groups[g];
+    a.ngroups = c->ngroups;
+    a.restore1 = c->restore1;
+    a.restore5 = c->restore5;
+    a.pw = c->prm.segment_bytes / 8;
+    a.bitmap = c->d_bitmap.p;
+    a.chunk_counts = c->d_chunk_counts.p;
+    if (timed && (e = hipEventRecord(c->ev[0], s)) != hipSuccess)
+        return e;
+    e = launch_sieve(a, c->prm.block_threads, (uint32_t)c->cus * c->prm.wg_per_cu, s);
+    if (e != hipSuccess)
+        return e;
+    if (timed && (e = hipEventRecord(c->ev[1], s)) != hipSuccess)
+        return e;
+    FinalizeArgs f;
+    f.job = job;
+    f.ranges = ranges;
+    f.counts = c->d_counts.p;
+    f.status = c->d_status.p;
+    f.chunk_counts = c->d_chunk_counts.p;
+    f.chunk_off = c->d_chunk_off.p;
+    if ((e = launch_finalize(f, kFinalizeGrid, s)) != hipSuccess)
+        return e;
+    CompactArgs k;
+    k.job = job;
+    k.ranges = ranges;
+    k.list_idx = (const uint32_t *)(c->d_blob.p + L.list_idx);
+    k.list_chunk0 = (const uint64_t *)(c->d_blob.p + L.list_chunk0);
+    k.status = c->d_status.p;
+    k.bitmap = c->d_bitmap.p;
+    k.chunk_off = c->d_chunk_off.p;
+    if ((e = launch_compact(k, (uint32_t)c->cus * 4, s)) != hipSuccess)
+        return e;
+    if (timed && (e = hipEventRecord(c->ev[2], s)) != hipSuccess)
+        return e;
+    return hipSuccess;
+}
+
+hipError_t capture_graph(sieve_ctx *c)
+{
+    if (c->graph) {
+        (void)hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    if (c->graph_src) {
+        (void)hipGraphDestroy(c->graph_src);
+        c->graph_src = nullptr;
+    }
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess)
+        return e;
+    hipError_t e2 = enqueue_kernels(c, c->stream, false);
+    e = hipStreamEndCapture(c->stream, &c->graph_src);
+    if (e2 != hipSuccess)
+        return e2;
+    if (e != hipSuccess)
+        return e;
+    e = hipGraphInstantiate(&c->graph, c->graph_src, nullptr, nullptr, 0);
+    if (e != hipSuccess)
+        return e;
+    c->graph_gen = c->gen;
+    return hipSuccess;
+}
+
+// Runs one job: plan, upload, kernels (graph or direct), results.
+// counts/status (host, n entries) receive per-range results.
+int run_job(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, const uint8_t *mode,
+            const uint64_t *off, const uint64_t *cap, int elem_bytes, void *out, uint64_t *counts,
+            int32_t *status, hipStream_t stream, bool use_graph)
+{
+    Plan pl;
+    int st = make_plan(c, n, lo, hi, mode, off, cap, elem_bytes, pl);
+    if (st != SIEVE_OK)
+        return st;
+    const uint64_t nlist = pl.list_idx.size();
+    if (nlist && !out)
+        return SIEVE_E_INVAL;
+    st = ensure_capacity(c, n, nlist, pl.nchunks);
+    if (st != SIEVE_OK)
+        return st;
+    hipStream_t s = stream ? stream : c->stream;
+    const BlobLayout L = blob_layout(c->cap_ranges, c->cap_list);
+    JobHeader *h = (JobHeader *)c->h_blob;
+    memset(h, 0, sizeof *h);
+    h->ntiles = pl.ntiles;
+    h->nchunks = pl.nchunks;
+    h->nranges = (uint32_t)n;
+    h->nlist = (uint32_t)nlist;
+    h->out = out;
+    h->elem_bytes = elem_bytes;
+    if (n)
+        memcpy(c->h_blob + L.ranges, pl.ranges.data(), n * sizeof(RangeDesc));
+    if (nlist) {
+        memcpy(c->h_blob + L.list_idx, pl.list_idx.data(), nlist * sizeof(uint32_t));
+        memcpy(c->h_blob + L.list_chunk0, pl.list_chunk0.data(), nlist * sizeof(uint64_t));
+    }
+    hipError_t e = hipMemcpyAsync(c->d_blob.p, c->h_blob, L.ranges + n * sizeof(RangeDesc),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && nlist)
+        e = hipMemcpyAsync(c->d_blob.p + L.list_idx, c->h_blob + L.list_idx,
+                           L.list_chunk0 - L.list_idx + nlist * sizeof(uint64_t), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess)
+        return hip_status(e);
+    if (use_graph) {
+        if (!c->graph || c->graph_gen != c->gen) {
+            // Capture on the context stream after the uploads are ordered.
+            if (s != c->stream) {
+                if ((e = hipStreamSynchronize(s)) != hipSuccess)
+                    return hip_status(e);
+            }
+            if ((e = capture_graph(c)) != hipSuccess)
+                return hip_status(e);
+        }
+        e = hipGraphLaunch(c->graph, s);
+    } else {
+        e = enqueue_kernels(c, s, c->timing != 0);
+    }
+    if (e != hipSuccess)
+        return hip_status(e);
+    if (n) {
+        e = hipMemcpyAsync(c->h_counts, c->d_counts.p, n * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->h_status, c->d_status.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess)
+            return hip_status(e);
+    }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_status(e);
+    if (c->timing && !use_graph) {
+        float a = 0, b = 0;
+        if (hipEventElapsedTime(&a, c->ev[0], c->ev[1]) == hipSuccess &&
+            hipEventElapsedTime(&b, c->ev[1], c->ev[2]) == hipSuccess) {
+            c->t_sieve_ms += a;
+            c->t_post_ms += b;
+            c->t_jobs++;
+        }
+    }
+    for (uint64_t i = 0; i < n; ++i) {
+        if (counts)
+            counts[i] = c->h_counts[i];
+        if (status)
+            status[i] = c->h_status[i];
+    }
+    return SIEVE_OK;
+}
+
+// Base primes: host sieve up to isqrt(limit) (at least 2^16), then the
+// device list path produces the rest straight into the resident set.
+int grow_base_primes(sieve_ctx *c, uint64_t limit)
+{
+    const uint64_t h = std::min<uint64_t>(limit, std::max<uint64_t>(isqrt_host(limit), 1u << 16));
+    if (c->limit < h) {
+        c->h_primes = host_small_primes(h);
+        int st = install_primes(c, h);
+        if (st != SIEVE_OK)
+            return st;
+    }
+    if (limit <= c->limit)
+        return SIEVE_OK;
+    const uint64_t lo = c->limit + 1, hi = limit + 1;
+    const uint64_t bound = sieve_list_bound(lo, hi);
+    uint32_t *d_out = nullptr;
+    if (hipMalloc((void **)&d_out, std::max<uint64_t>(bound, 1) * sizeof(uint32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        return SIEVE_E_NOMEM;
+    }
+    const uint8_t mode = 1;
+    const uint64_t off = 0;
+    uint64_t cnt = 0;
+    int32_t rs = 0;
+    int st = run_job(c, 1, &lo, &hi, &mode, &off, &bound, 4, d_out, &cnt, &rs, nullptr, false);
+    if (st == SIEVE_OK && rs != SIEVE_OK)
+        st = rs;
+    if (st == SIEVE_OK) {
+        const size_t old = c->h_primes.size();
+        c->h_primes.resize(old + cnt);
+        hipError_t e = hipMemcpy(c->h_primes.data() + old, d_out, cnt * sizeof(uint32_t), hipMemcpyDeviceToHost);
+        st = hip_status(e);
+        if (st == SIEVE_OK)
+            st = install_primes(c, limit);
+    }
+    (void)hipFree(d_out);
+    return st;
+}
+
+void destroy_ctx(sieve_ctx *c)
+{
+    if (!c)
+        return;
+    if (c->graph)
+        (void)hipGraphExecDestroy(c->graph);
+    if (c->graph_src)
+        (void)hipGraphDestroy(c->graph_src);
+    c->d_prm.release();
+    c->d_rcp.release();
+    c->d_pidx.release();
+    c->d_items.release();
+    c->d_item_prefix.release();
+    c->d_pstab.release();
+    c->d_blob.release();
+    c->d_counters.release();
+    c->d_counts.release();
+    c->d_status.release();
+    c->d_bitmap.release();
+    c->d_chunk_counts.release();
+    c->d_chunk_off.release();
+    if (c->h_blob)
+        (void)hipHostFree(c->h_blob);
+    if (c->h_counts)
+        (void)hipHostFree(c->h_counts);
+    if (c->h_status)
+        (void)hipHostFree(c->h_status);
+    for (auto &ev : c->ev)
+        if (ev)
+            (void)hipEventDestroy(ev);
+    if (c->stream)
+        (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sieve_strerror(int s)
+{
+    switch (s) {
+    case SIEVE_OK:
+        return "ok";
+    case SIEVE_E_INVAL:
+        return "invalid argument";
+    case SIEVE_E_RANGE:
+        return "base primes do not cover isqrt(hi - 1)";
+    case SIEVE_E_CAPACITY:
+        return "output capacity too small";
+    case SIEVE_E_DTYPE:
+        return "element size not 4/8, or uint32 output for values >= 2^32";
+    case SIEVE_E_NOMEM:
+        return "out of memory";
+    case SIEVE_E_DEVICE:
+        return "HIP device error";
+    case SIEVE_E_BUSY:
+        return "busy";
+    case SIEVE_E_CANCELLED:
+        return "cancelled";
+    default:
+        return "unknown status";
+    }
+}
+
+int sieve_last_error(const sieve_ctx *ctx) { return ctx ? ctx->last_error : SIEVE_E_INVAL; }
+
+int sieve_default_params(sieve_params *p)
+{
+    if (!p)
+        return SIEVE_E_INVAL;
+    memset(p, 0, sizeof *p);
+    fill_defaults(*p);
+    return SIEVE_OK;
+}
+
+int sieve_create(sieve_ctx **out, int device, const sieve_params *p)
+{
+    if (!out)
+        return SIEVE_E_INVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        (void)hipGetLastError();
+        return SIEVE_E_DEVICE;
+    }
+    if (device < 0 || device >= ndev)
+        return SIEVE_E_INVAL;
+    hipDeviceProp_t prop;
+    if (hipSetDevice(device) != hipSuccess || hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        (void)hipGetLastError();
+        return SIEVE_E_DEVICE;
+    }
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return SIEVE_E_DEVICE;  // the kernels are built for gfx950 only
+    sieve_ctx *c = new (std::nothrow) sieve_ctx();
+    if (!c)
+        return SIEVE_E_NOMEM;
+    c->device = device;
+    c->cus = prop.multiProcessorCount;
+    // CDNA4 gives a workgroup up to 160 KiB of LDS.
+    c->lds_max = 160 * 1024;
+    sieve_params q;
+    memset(&q, 0, sizeof q);
+    if (p)
+        q = *p;
+    fill_defaults(q);
+    int st = validate_params(q, c->lds_max);
+    if (st != SIEVE_OK) {
+        destroy_ctx(c);
+        return st;
+    }
+    c->prm = q;
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
+        set_sieve_lds_limit(q.segment_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        destroy_ctx(c);
+        return SIEVE_E_DEVICE;
+    }
+    for (auto &ev : c->ev)
+        if (hipEventCreate(&ev) != hipSuccess) {
+            (void)hipGetLastError();
+            destroy_ctx(c);
+            return SIEVE_E_DEVICE;
+        }
+    st = build_presieve(c, q.presieve_groups == SIEVE_PRESIEVE_NONE ? 0 : q.presieve_groups);
+    if (st == SIEVE_OK)
+        st = install_primes(c, 0);
+    if (st == SIEVE_OK)
+        st = ensure_capacity(c, 1, 1, 1);
+    if (st != SIEVE_OK) {
+        destroy_ctx(c);
+        return st;
+    }
+    *out = c;
+    return SIEVE_OK;
+}
+
+int sieve_destroy(sieve_ctx *ctx)
+{
+    if (ctx) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipStreamSynchronize(ctx->stream);
+    }
+    destroy_ctx(ctx);
+    return SIEVE_OK;
+}
+
+int sieve_get_params(const sieve_ctx *ctx, sieve_params *p)
+{
+    if (!ctx || !p)
+        return SIEVE_E_INVAL;
+    *p = ctx->prm;
+    return SIEVE_OK;
+}
+
+int sieve_base_primes(sieve_ctx *ctx, uint64_t limit, uint64_t *n_out)
+{
+    if (!ctx)
+        return SIEVE_E_INVAL;
+    if (limit >= (1ull << 32))
+        return set_err(ctx, SIEVE_E_INVAL);
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return set_err(ctx, hip_status(hipErrorInvalidDevice));
+    int st = SIEVE_OK;
+    if (limit > ctx->limit)
+        st = grow_base_primes(ctx, limit);
+    if (st == SIEVE_OK && n_out)
+        *n_out = ctx->h_primes.size();
+    return set_err(ctx, st);
+}
+
+int sieve_base_limit(const sieve_ctx *ctx, uint64_t *limit)
+{
+    if (!ctx || !limit)
+        return SIEVE_E_INVAL;
+    *limit = ctx->limit;
+    return SIEVE_OK;
+}
+
+int sieve_count(sieve_ctx *ctx, uint64_t lo, uint64_t hi, uint64_t *count)
+{
+    if (!ctx || !count)
+        return set_err(ctx, SIEVE_E_INVAL);
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return set_err(ctx, SIEVE_E_DEVICE);
+    int32_t rs = 0;
+    int st = run_job(ctx, 1, &lo, &hi, nullptr, nullptr, nullptr, 8, nullptr, count, &rs, nullptr, false);
+    return set_err(ctx, st);
+}
+
+int sieve_list(sieve_ctx *ctx, uint64_t lo, uint64_t hi, void *out_dev, uint64_t cap, int elem_bytes,
+               uint64_t *n_out, void *stream)
+{
+    if (!ctx || !n_out)
+        return set_err(ctx, SIEVE_E_INVAL);
+    if (elem_bytes != 4 && elem_bytes != 8)
+        return set_err(ctx, SIEVE_E_DTYPE);
+    if (!out_dev && cap)
+        return set_err(ctx, SIEVE_E_INVAL);
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return set_err(ctx, SIEVE_E_DEVICE);
+    const uint8_t mode = 1;
+    const uint64_t off = 0;
+    int32_t rs = 0;
+    // A NULL output with cap 0 only asks for the count.
+    void *out = out_dev ? out_dev : (void *)ctx->d_chunk_off.p;
+    int st = run_job(ctx, 1, &lo, &hi, &mode, &off, &cap, elem_bytes, out, n_out, &rs, (hipStream_t)stream,
+                     false);
+    if (st == SIEVE_OK && rs != SIEVE_OK)
+        st = rs;
+    return set_err(ctx, st);
+}
+
+int sieve_count_batch(sieve_ctx *ctx, const uint64_t *lo, const uint64_t *hi, uint64_t n, uint64_t *counts,
+                      void *stream)
+{
+    if (!ctx || (n && (!lo || !hi || !counts)) || n > 0xFFFFFFFFull)
+        return set_err(ctx, SIEVE_E_INVAL);
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return set_err(ctx, SIEVE_E_DEVICE);
+    if (n == 0)
+        return set_err(ctx, SIEVE_OK);
+    int st = run_job(ctx, n, lo, hi, nullptr, nullptr, nullptr, 8, nullptr, counts, nullptr,
+                     (hipStream_t)stream, ctx->prm.use_graph != 0);
+    return set_err(ctx, st);
+}
+
+int sieve_list_batch(sieve_ctx *ctx, const uint64_t *lo, const uint64_t *hi, const uint8_t *mode, uint64_t n,
+                     void *out_dev, const uint64_t *off, const uint64_t *cap, int elem_bytes, uint64_t *counts,
+                     int32_t *status, void *stream)
+{
+    if (!ctx || (n && (!lo || !hi || !mode || !counts || !status)) || n > 0xFFFFFFFFull)
+        return set_err(ctx, SIEVE_E_INVAL);
+    if (elem_bytes != 4 && elem_bytes != 8)
+        return set_err(ctx, SIEVE_E_DTYPE);
+    bool any = false;
+    for (uint64_t i = 0; i < n; ++i)
+        any |= mode[i] != 0;
+    if (any && (!out_dev || !off || !cap))
+        return set_err(ctx, SIEVE_E_INVAL);
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return set_err(ctx, SIEVE_E_DEVICE);
+    if (n == 0)
+        return set_err(ctx, SIEVE_OK);
+    int st = run_job(ctx, n, lo, hi, mode, off, cap, elem_bytes, out_dev, counts, status, (hipStream_t)stream,
+                     ctx->prm.use_graph != 0);
+    return set_err(ctx, st);
+}
+
+uint64_t sieve_list_bound(uint64_t lo, uint64_t hi)
+{
+    if (hi <= lo)
+        return 0;
+    // Values coprime to 6 in [lo, hi), plus 2 and 3.
+    auto cop = [](uint64_t x) -> uint64_t {  // #{1 <= m < x : gcd(m, 6) = 1}
+        if (x == 0)
+            return 0;
+        const uint64_t n = x - 1, q = n / 6, s = n % 6;
+        return 2 * q + (s >= 1) + (s >= 5);
+    };
+    uint64_t b = cop(hi) - cop(lo) + 2;
+    const uint64_t y = hi - lo;
+    if (y > 1) {
+        // Brun-Titchmarsh (Montgomery-Vaughan): pi(x + y) - pi(x) < 2y / ln y.
+        const double bt = 2.0 * (double)y / std::log((double)y);
+        if (bt < 1.8e19) {
+            const uint64_t b2 = (uint64_t)std::ceil(bt * (1.0 + 1e-9)) + 1;
+            if (b2 < b)
+                b = b2;
+        }
+    }
+    return b;
+}
+
+int sieve_wheel_start(uint64_t p, uint64_t base, uint64_t M, int64_t *id1, int64_t *id5)
+{
+    if (!id1 || !id5 || p < 5 || (p % 6 != 1 && p % 6 != 5) || base % 6 || M < 1 || M < base ||
+        M - base >= (1ull << 40) || p >= (1ull << 32))
+        return SIEVE_E_INVAL;
+    int64_t a, b;
+    wheel_start(p, p / 6, UINT64_MAX / p, base, M, a, b);
+    *id1 = a;
+    *id5 = b;
+    return SIEVE_OK;
+}
+
+int sieve_plan_range(uint64_t lo, uint64_t hi, uint32_t segment_bytes, uint64_t *ntiles, uint64_t *base,
+                     uint32_t *last_words)
+{
+    if (!ntiles || !base || !last_words || lo > hi || hi > SIEVE_MAX_HI || segment_bytes < 8192 ||
+        segment_bytes % 4096)
+        return SIEVE_E_INVAL;
+    plan_range(lo, hi, segment_bytes / 8, *ntiles, *base, *last_words);
+    return SIEVE_OK;
+}
+
+int sieve_set_timing(sieve_ctx *ctx, int on)
+{
+    if (!ctx)
+        return SIEVE_E_INVAL;
+    ctx->timing = on;
+    ctx->t_sieve_ms = ctx->t_post_ms = 0;
+    ctx->t_jobs = 0;
+    return SIEVE_OK;
+}
+
+int sieve_get_timing(const sieve_ctx *ctx, double *sieve_ms, double *post_ms, uint64_t *jobs)
+{
+    if (!ctx || !sieve_ms || !post_ms || !jobs)
+        return SIEVE_E_INVAL;
+    *sieve_ms = ctx->t_sieve_ms;
+    *post_ms = ctx->t_post_ms;
+    *jobs = ctx->t_jobs;
+    return SIEVE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,503 @@
+// Device kernels of the segmented wheel sieve (gfx950, wave64).
+//
+// k_sieve      one persistent launch over every tile of a job.  Per tile, in
+//              LDS: presieve init, Table 1 starts + marking of the remaining
+//              base primes, edge masks, then either a popcount into the
+//              range's count or a value-ordered bitmap + per-chunk counts.
+// k_finalize   per range: adds 2 and 3 when in range; for list ranges an
+//              exclusive scan of the chunk counts gives each chunk's output
+//              offset, and the capacity check sets the range status.
+// k_compact    per bitmap chunk: popcount, block prefix, LDS staging and
+//              coalesced stores of the primes as uint32 or uint64.
+#include "sieve_internal.h"
+#include "wheel.h"
+
+namespace sieve {
+
+namespace {
+
+constexpr uint32_t kWave = 64;
+
+__device__ inline uint64_t isqrt_dev(uint64_t x)
+{
+    if (x < 2)
+        return x;
+    uint64_t s = (uint64_t)sqrt((double)x);
+    while (s * s > x)
+        --s;
+    while ((s + 1) * (s + 1) <= x)
+        ++s;
+    return s;
+}
+
+__device__ inline uint32_t wave_sum(uint32_t x)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1)
+        x += __shfl_xor(x, d, kWave);
+    return x;
+}
+
+__device__ inline uint32_t wave_incl_scan(uint32_t x, uint32_t lane)
+{
+#pragma unroll
+    for (uint32_t d = 1; d < kWave; d <<= 1) {
+        uint32_t y = __shfl_up(x, d, kWave);
+        if (lane >= d)
+            x += y;
+    }
+    return x;
+}
+
+// Spreads the 32 bits of x to the even bit positions of a 64-bit word
+// (interleaving by binary magic numbers, as in S. E. Anderson's
+// "Bit Twiddling Hacks").
+__device__ inline uint64_t spread32(uint32_t x)
+{
+    uint64_t v = x;
+    v = (v | (v << 16)) & 0x0000FFFF0000FFFFull;
+    v = (v | (v << 8)) & 0x00FF00FF00FF00FFull;
+    v = (v | (v << 4)) & 0x0F0F0F0F0F0F0F0Full;
+    v = (v | (v << 2)) & 0x3333333333333333ull;
+    v = (v | (v << 1)) & 0x5555555555555555ull;
+    return v;
+}
+
+__device__ inline void lds_set(uint32_t *pl, uint32_t i)
+{
+    atomicOr(&pl[i >> 5], 1u << (i & 31));
+}
+
+// Clears (sets the composite bit of) start, start + step, ... below nbits.
+// The paper strides by P indices in each array (Sec. 3: adding P to the
+// index adds 6P to the value and keeps the residue mod 6).
+__device__ inline void mark_plane(uint32_t *pl, int64_t start, uint32_t step, uint32_t nbits)
+{
+    if (start >= (int64_t)nbits)
+        return;
+    uint32_t i = (uint32_t)start;
+    if (step < (nbits >> 2)) {
+        for (; i + 3 * step < nbits; i += 4 * step) {
+            lds_set(pl, i);
+            lds_set(pl, i + step);
+            lds_set(pl, i + 2 * step);
+            lds_set(pl, i + 3 * step);
+        }
+    }
+    for (; i < nbits; i += step)
+        lds_set(pl, i);
+}
+
+}  // namespace
+
+template <int NT>
+__global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
+{
+    extern __shared__ uint32_t lds[];
+    __shared__ unsigned long long s_tile;
+    __shared__ uint32_t s_range;
+    __shared__ uint32_t s_nact;
+    __shared__ uint32_t s_psoff[kMaxGroups];
+    __shared__ uint32_t s_red[NT / kWave];
+    __shared__ uint32_t s_chunk[64];
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & (kWave - 1);
+    const uint32_t wave = tid / kWave;
+    const uint32_t pw = a.pw;
+    uint32_t *pl1 = lds;
+    uint32_t *pl5 = lds + pw;
+    const uint64_t ntiles = a.job->ntiles;
+    const uint32_t nranges = a.job->nranges;
+
+    for (;;) {
+        if (tid == 0) {
+            const unsigned long long t = atomicAdd(&a.counters[kTileCounter], 1ull);
+            s_tile = t;
+            if (t < ntiles) {
+                // Last range whose first tile is <= t.
+                uint32_t lo = 0, hi = nranges;
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (a.ranges[mid].tile0 <= t)
+                        lo = mid;
+                    else
+                        hi = mid;
+                }
+                s_range = lo;
+                const RangeDesc &d = a.ranges[lo];
+                const uint64_t k = t - d.tile0;
+                const uint32_t nw = (k + 1 == d.ntiles) ? d.last_words : pw;
+                const uint64_t tend = d.base + k * kValsPerWord * pw + kValsPerWord * nw;
+                // Primes p with p * p < tile end (Sec. 4: only primes up to
+                // the square root sieve anything); pidx over-counts by the
+                // few primes in the last 64-wide step, which mark nothing.
+                uint64_t s = (isqrt_dev(tend - 1) + 63) / 64;
+                if (s >= a.pidx_len)
+                    s = a.pidx_len - 1;
+                s_nact = a.pidx[s];
+            }
+        }
+        if (tid < 64)
+            s_chunk[tid] = 0;
+        __syncthreads();
+        const unsigned long long t = s_tile;
+        if (t >= ntiles)
+            break;
+        const RangeDesc &d = a.ranges[s_range];
+        const uint64_t k = t - d.tile0;
+        const bool first = (k == 0);
+        const bool last = (k + 1 == d.ntiles);
+        const uint32_t nwords = last ? d.last_words : pw;
+        const uint64_t B = d.base + k * kValsPerWord * pw;  // tile value base, multiple of 6
+        const uint64_t tend = B + kValsPerWord * nwords;
+        const uint32_t nbits = nwords * 32;
+
+        // ---- presieve init: OR of the repeating composite patterns -------
+        if (tid < a.ngroups)
+            s_psoff[tid] = (uint32_t)((B / 6) % a.groups[tid].period);
+        __syncthreads();
+        {
+            uint32_t o[kMaxGroups];
+#pragma unroll
+            for (int g = 0; g < kMaxGroups; ++g)
+                if (g < (int)a.ngroups)
+                    o[g] = (s_psoff[g] + 32u * tid) % a.groups[g].period;
+            for (uint32_t w = tid; w < nwords; w += NT) {
+                uint32_t c1 = 0, c5 = 0;
+#pragma unroll
+                for (int g = 0; g < kMaxGroups; ++g) {
+                    if (g < (int)a.ngroups) {
+                        const uint2 *tb = a.ps_tab + a.groups[g].offset + (o[g] >> 5);
+                        const uint2 x = tb[0];
+                        const uint2 y = tb[1];
+                        const uint32_t sh = o[g] & 31;
+                        c1 |= __builtin_amdgcn_alignbit(y.x, x.x, sh);
+                        c5 |= __builtin_amdgcn_alignbit(y.y, x.y, sh);
+                        o[g] += a.groups[g].step;
+                        if (o[g] >= a.groups[g].period)
+                            o[g] -= a.groups[g].period;
+                    }
+                }
+                pl1[w] = c1;
+                pl5[w] = c5;
+            }
+        }
+        __syncthreads();
+
+        // ---- marking: Table 1 starts, stride P in each plane -------------
+        {
+            const uint32_t n_act = s_nact;
+            const uint32_t ks = n_act < a.k_split ? n_act : a.k_split;
+            const uint32_t n_items = ks > a.first_mark ? a.item_prefix[ks - a.first_mark] : 0;
+            const uint32_t n_rest = n_act > a.k_split ? n_act - a.k_split : 0;
+            const uint32_t n_work = n_items + n_rest;
+            for (uint32_t v = tid; v < n_work; v += NT) {
+                uint32_t kp, j, g;
+                if (v < n_items) {
+                    const uint2 it = a.items[v];
+                    kp = it.x;
+                    j = it.y >> 16;
+                    g = it.y & 0xFFFFu;
+                } else {
+                    kp = a.k_split + (v - n_items);
+                    j = 0;
+                    g = 1;
+                }
+                const uint2 pr = a.prm[kp];
+                const uint64_t P = pr.x;
+                const uint64_t P2 = P * P;
+                const uint64_t M = P2 > B ? P2 : B;
+                if (M >= tend)
+                    continue;
+                int64_t id1, id5;
+                wheel_start(P, pr.y, a.rcp[kp], B, M, id1, id5);
+                const uint32_t step = g * pr.x;
+                mark_plane(pl1, id1 + (int64_t)j * (int64_t)P, step, nbits);
+                mark_plane(pl5, id5 + (int64_t)j * (int64_t)P, step, nbits);
+            }
+        }
+        __syncthreads();
+
+        // ---- edges, then count or bitmap ---------------------------------
+        uint32_t head1 = 0, head5 = 0, tail1 = 0, tail5 = 0;
+        if (first) {
+            if (B + 1 < d.lo || B == 0)
+                head1 = 1;  // below lo, or the value 1
+            if (B + 5 < d.lo)
+                head5 = 1;
+        }
+        if (last) {
+            const uint64_t base_i = 32ull * (nwords - 1);
+            const uint64_t n1 = d.hi > B + 1 ? (d.hi - B - 1 + 5) / 6 : 0;
+            const uint64_t n5 = d.hi > B + 5 ? (d.hi - B - 5 + 5) / 6 : 0;
+            const uint64_t r1 = n1 > base_i ? n1 - base_i : 0;
+            const uint64_t r5 = n5 > base_i ? n5 - base_i : 0;
+            tail1 = r1 >= 32 ? 0u : (~0u << r1);
+            tail5 = r5 >= 32 ? 0u : (~0u << r5);
+        }
+        const bool list = d.mode != 0;
+        const uint32_t nw_pad = list ? ((nwords + kChunkWords - 1) / kChunkWords) * kChunkWords : nwords;
+        const uint64_t wbase = list ? (d.chunk0 + k * (pw / kChunkWords)) * kChunkWords : 0;
+        uint32_t cnt = 0;
+        for (uint32_t w = tid; w < nw_pad; w += NT) {
+            uint32_t p1 = 0, p5 = 0;
+            if (w < nwords) {
+                uint32_t c1 = pl1[w], c5 = pl5[w];
+                if (w == 0 && B == 0) {
+                    c1 &= ~a.restore1;  // the presieved primes themselves
+                    c5 &= ~a.restore5;
+                }
+                if (w == 0) {
+                    c1 |= head1;
+                    c5 |= head5;
+                }
+                if (w == nwords - 1) {
+                    c1 |= tail1;
+                    c5 |= tail5;
+                }
+                p1 = ~c1;
+                p5 = ~c5;
+            }
+            const uint32_t c = __popc(p1) + __popc(p5);
+            if (list) {
+                a.bitmap[wbase + w] = spread32(p1) | (spread32(p5) << 1);
+                const uint32_t ws = wave_sum(c);
+                if (lane == 0)
+                    atomicAdd(&s_chunk[w / kChunkWords], ws);
+            } else {
+                cnt += c;
+            }
+        }
+        if (list) {
+            __syncthreads();
+            const uint32_t nch = nw_pad / kChunkWords;
+            const uint64_t cbase = d.chunk0 + k * (pw / kChunkWords);
+            if (tid < nch)
+                a.chunk_counts[cbase + tid] = s_chunk[tid];
+        } else {
+            cnt = wave_sum(cnt);
+            if (lane == 0)
+                s_red[wave] = cnt;
+            __syncthreads();
+            if (tid == 0) {
+                uint32_t tot = 0;
+                for (uint32_t i = 0; i < NT / kWave; ++i)
+                    tot += s_red[i];
+                atomicAdd(&a.counts[s_range], (unsigned long long)tot);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kFinalizeThreads) k_finalize(FinalizeArgs a)
+{
+    __shared__ uint32_t s_w[kFinalizeThreads / kWave];
+    __shared__ unsigned long long s_carry;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & (kWave - 1);
+    const uint32_t wave = tid / kWave;
+    const uint32_t nranges = a.job->nranges;
+
+    for (uint32_t r = blockIdx.x; r < nranges; r += gridDim.x) {
+        const RangeDesc &d = a.ranges[r];
+        // 2 and 3 lie outside the wheel (Sec. 2.1) and are reported when in range.
+        const uint32_t has2 = (d.lo <= 2 && 2 < d.hi) ? 1u : 0u;
+        const uint32_t has3 = (d.lo <= 3 && 3 < d.hi) ? 1u : 0u;
+        const uint32_t sp = has2 + has3;
+        if (d.mode == 0) {
+            if (tid == 0) {
+                a.counts[r] += sp;
+                a.status[r] = 0;
+            }
+            continue;
+        }
+        if (tid == 0)
+            s_carry = 0;
+        __syncthreads();
+        for (uint32_t b0 = 0; b0 < d.nchunks; b0 += kFinalizeThreads) {
+            const uint32_t i = b0 + tid;
+            const uint32_t c = i < d.nchunks ? a.chunk_counts[d.chunk0 + i] : 0u;
+            const uint32_t incl = wave_incl_scan(c, lane);
+            if (lane == kWave - 1)
+                s_w[wave] = incl;
+            __syncthreads();
+            uint32_t woff = 0, btot = 0;
+            for (uint32_t q = 0; q < kFinalizeThreads / kWave; ++q) {
+                woff += q < wave ? s_w[q] : 0u;
+                btot += s_w[q];
+            }
+            if (i < d.nchunks)
+                a.chunk_off[d.chunk0 + i] = d.out_off + sp + s_carry + woff + incl - c;
+            __syncthreads();
+            if (tid == 0)
+                s_carry += btot;
+            __syncthreads();
+        }
+        if (tid == 0) {
+            const unsigned long long total = s_carry + sp;
+            a.counts[r] = total;
+            if (total > d.cap) {
+                a.status[r] = -3;  // SIEVE_E_CAPACITY
+            } else {
+                a.status[r] = 0;
+                uint64_t pos = d.out_off;
+                if (a.job->elem_bytes == 4) {
+                    uint32_t *o = (uint32_t *)a.job->out;
+                    if (has2)
+                        o[pos++] = 2;
+                    if (has3)
+                        o[pos++] = 3;
+                } else {
+                    uint64_t *o = (uint64_t *)a.job->out;
+                    if (has2)
+                        o[pos++] = 2;
+                    if (has3)
+                        o[pos++] = 3;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kCompactThreads) k_compact(CompactArgs a)
+{
+    constexpr uint32_t kW = kCompactThreads / kWave;
+    __shared__ T s_stage[kW][kStagePerWave];
+    __shared__ uint32_t s_wt[kW];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & (kWave - 1);
+    const uint32_t wave = tid / kWave;
+    if (a.job->elem_bytes != (int32_t)sizeof(T))
+        return;
+    const uint64_t nchunks = a.job->nchunks;
+    const uint32_t nlist = a.job->nlist;
+
+    for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        // List range holding chunk c: the last one whose chunk0 <= c.
+        uint32_t lo = 0, hi = nlist;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (a.list_chunk0[mid] <= c)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const uint32_t r = a.list_idx[lo];
+        if (a.status[r] != 0)
+            continue;  // over capacity: nothing is written for this range
+        const RangeDesc &d = a.ranges[r];
+        uint64_t m = a.bitmap[c * kChunkWords + tid];
+        const uint32_t cnt = __popcll(m);
+        const uint32_t incl = wave_incl_scan(cnt, lane);
+        if (lane == kWave - 1)
+            s_wt[wave] = incl;
+        __syncthreads();
+        uint32_t woff = 0, wmax = 0;
+        for (uint32_t q = 0; q < kW; ++q) {
+            woff += q < wave ? s_wt[q] : 0u;
+            wmax = s_wt[q] > wmax ? s_wt[q] : wmax;
+        }
+        const uint32_t wtot = s_wt[wave];
+        const uint64_t obase = a.chunk_off[c] + woff;
+        const uint64_t vb = d.base + kChunkVals * (c - d.chunk0) + kValsPerWord * tid;
+        const uint32_t excl = incl - cnt;
+        T *out = (T *)a.job->out;
+        // Passes over rank windows of kStagePerWave, uniform across the block.
+        for (uint32_t pass = 0; pass < wmax; pass += kStagePerWave) {
+            if (excl < pass + kStagePerWave && excl + cnt > pass) {
+                uint64_t mm = m;
+                uint32_t pos = excl;
+                while (mm) {
+                    const uint32_t b = (uint32_t)__builtin_ctzll(mm);
+                    mm &= mm - 1;
+                    if (pos >= pass && pos < pass + kStagePerWave)
+                        s_stage[wave][pos - pass] = (T)(vb + 3ull * b + 1ull + (b & 1u));
+                    ++pos;
+                }
+            }
+            __syncthreads();
+            if (wtot > pass) {
+                const uint32_t n_in = (wtot - pass) < kStagePerWave ? (wtot - pass) : kStagePerWave;
+                for (uint32_t e = lane; e < n_in; e += kWave)
+                    out[obase + pass + e] = s_stage[wave][e];
+            }
+            __syncthreads();
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_zero(const JobHeader *job, unsigned long long *counters, unsigned long long *counts)
+{
+    const uint32_t n = job->nranges;
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < kNumCounters)
+        counters[g] = 0;
+    for (uint32_t i = g; i < n; i += gridDim.x * blockDim.x)
+        counts[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launch helpers (called from the runtime in api.hip).
+// ---------------------------------------------------------------------------
+hipError_t set_sieve_lds_limit(uint32_t bytes)
+{
+    hipError_t e;
+    e = hipFuncSetAttribute((const void *)k_sieve<256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess)
+        return e;
+    e = hipFuncSetAttribute((const void *)k_sieve<512>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess)
+        return e;
+    return hipFuncSetAttribute((const void *)k_sieve<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_zero(const JobHeader *job, unsigned long long *counters, unsigned long long *counts,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero, dim3(64), dim3(256), 0, s, job, counters, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_sieve(const SieveArgs &a, uint32_t nt, uint32_t grid, hipStream_t s)
+{
+    const size_t lds = (size_t)a.pw * 8;
+    switch (nt) {
+    case 256:
+        hipLaunchKernelGGL(k_sieve<256>, dim3(grid), dim3(256), lds, s, a);
+        break;
+    case 512:
+        hipLaunchKernelGGL(k_sieve<512>, dim3(grid), dim3(512), lds, s, a);
+        break;
+    case 1024:
+        hipLaunchKernelGGL(k_sieve<1024>, dim3(grid), dim3(1024), lds, s, a);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const FinalizeArgs &a, uint32_t grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(kFinalizeThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+// Both element types are launched; each kernel exits at once unless the job's
+// element size is its own, so one launch sequence (and one graph) fits all.
+hipError_t launch_compact(const CompactArgs &a, uint32_t grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_compact<uint32_t>, dim3(grid), dim3(kCompactThreads), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_compact<uint64_t>, dim3(grid), dim3(kCompactThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace sieve

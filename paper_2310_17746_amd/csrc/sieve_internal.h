@@ -1,0 +1,114 @@
+// Internal layout shared by the HIP kernels and the host runtime of libsieve.
+//
+// Value layout (Sec. 2.1, Fig. 2): a tile with value base B (a multiple of
+// 6) holds two bit planes of PW 32-bit words each in LDS.  Bit i of plane
+// A_r (r = 1 or 5) stands for the value B + 6*i + r.  One plane word covers
+// 192 consecutive integers; a tile covers 192 * PW integers.  In LDS a set
+// bit means "composite / excluded" so that marking is a single LDS OR.
+//
+// List output goes through a value-ordered bitmap in HBM: plane word w of
+// A_one and A_five are interleaved into one 64-bit word whose bit 2i is
+// B + 192w + 6i + 1 and bit 2i+1 is B + 192w + 6i + 5, set when prime.
+// Bitmap words are grouped in chunks of kChunkWords; chunk c of a range
+// starts at value base + kChunkVals * c.
+#pragma once
+
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+namespace sieve {
+
+constexpr uint32_t kChunkWords = 512;                       // u64 bitmap words per chunk
+constexpr uint64_t kValsPerWord = 192;                      // integers per plane word
+constexpr uint64_t kChunkVals = kValsPerWord * kChunkWords;  // integers per chunk
+constexpr int kMaxGroups = 5;                               // presieve pattern groups
+constexpr uint32_t kCompactThreads = 512;                   // one bitmap word per thread
+constexpr uint32_t kStagePerWave = 512;                     // compaction staging entries per wave
+constexpr uint32_t kFinalizeThreads = 1024;
+
+// One range of a job.  Host-computed plan; read-only on the device.
+struct RangeDesc {
+    uint64_t lo, hi;     // [lo, hi)
+    uint64_t base;       // lo - lo % 6: value base of tile 0
+    uint64_t tile0;      // global index of the range's first tile
+    uint64_t chunk0;     // list ranges: global index of the first bitmap chunk
+    uint64_t out_off;    // list ranges: first output element
+    uint64_t cap;        // list ranges: output capacity in elements
+    uint32_t ntiles;     // tiles of this range (0 when it holds no wheel value)
+    uint32_t last_words; // plane words of the last tile
+    uint32_t mode;       // 0 count, 1 list
+    uint32_t nchunks;    // list ranges: bitmap chunks
+};
+
+// Per-job scalars, in device memory so that a captured graph can be replayed
+// for a new job after only a host-to-device copy.
+struct JobHeader {
+    uint64_t ntiles;     // tiles over all ranges
+    uint64_t nchunks;    // bitmap chunks over all list ranges
+    uint32_t nranges;
+    uint32_t nlist;      // list ranges
+    void *out;           // caller's output buffer (list ranges)
+    int32_t elem_bytes;  // 4 or 8
+    int32_t pad;
+};
+
+// Counters zeroed at the start of every job.
+enum Counter { kTileCounter = 0, kChunkCounter = 1, kNumCounters = 4 };
+
+// A presieve pattern group: primes whose product is `period`.  Its table
+// holds period + 64 bits per plane (bit t stands for 6t + r, set when some
+// prime of the group divides it), stored as uint2 {A_one word, A_five word}
+// at `offset` words into the shared table.
+struct PsGroup {
+    uint32_t period;
+    uint32_t offset;
+    uint32_t step;  // (32 * block_threads) mod period
+    uint32_t pad;
+};
+
+// Kernel arguments: pointers and context-level constants only.  Everything
+// that changes from job to job lives in JobHeader / RangeDesc on the device.
+struct SieveArgs {
+    const JobHeader *job;
+    const RangeDesc *ranges;
+    unsigned long long *counters;
+    unsigned long long *counts;   // per range
+    const uint2 *prm;             // {p, p / 6} for every resident prime >= 5, ascending
+    const uint64_t *rcp;          // floor((2^64 - 1) / p)
+    const uint32_t *pidx;         // pidx[s] = number of resident primes <= 64 * s
+    uint32_t pidx_len;
+    uint32_t nprimes;
+    uint32_t first_mark;          // first prime index marked in LDS (after the presieve)
+    uint32_t k_split;             // primes [first_mark, k_split) are split into items
+    const uint2 *items;           // {prime index, (j << 16) | g}
+    const uint32_t *item_prefix;  // items before prime first_mark + i
+    const uint2 *ps_tab;
+    PsGroup groups[kMaxGroups];
+    uint32_t ngroups;
+    uint32_t restore1, restore5;  // word-0 bits of presieved primes (tile base 0)
+    uint32_t pw;                  // plane words per tile
+    unsigned long long *bitmap;   // list scratch (u64 words)
+    uint32_t *chunk_counts;       // per chunk prime count
+};
+
+struct FinalizeArgs {
+    const JobHeader *job;
+    const RangeDesc *ranges;
+    unsigned long long *counts;
+    int32_t *status;
+    const uint32_t *chunk_counts;
+    unsigned long long *chunk_off;
+};
+
+struct CompactArgs {
+    const JobHeader *job;
+    const RangeDesc *ranges;
+    const uint32_t *list_idx;     // range index of each list range, ascending chunk0
+    const uint64_t *list_chunk0;  // chunk0 of each list range
+    const int32_t *status;
+    const unsigned long long *bitmap;
+    const unsigned long long *chunk_off;
+};
+
+}  // namespace sieve

@@ -1,0 +1,115 @@
+"""Host-side logic of the library, checked on the CPU (no device work).
+
+* The C ABI loads and exports every function include/sieve.h declares.
+* Table 1 as evaluated by the library's own wheel code (compiled for the
+  host) equals the oracle's definition "first multiple of P >= M in the
+  class", and reproduces the paper's worked example (Sec. 3).
+* The tile planner covers every wheel value of a range exactly once.
+* sieve_list_bound is an upper bound on the oracle's counts.
+"""
+import os
+import random
+import re
+
+import pytest
+
+import oracle
+from oracle import wheel
+from conftest import ROOT, read_golden
+
+pkg = pytest.importorskip("paper_2310_17746_amd")
+
+
+def _declared_functions():
+    hdr = open(os.path.join(ROOT, "include", "sieve.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    return sorted(set(re.findall(r"\b(sieve_[a-z_0-9]+)\s*\(", hdr)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pkg.load_library()
+    names = _declared_functions()
+    assert "sieve_count" in names and "sieve_list_batch" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_worked_example_through_library():
+    (row,) = read_golden("table1_worked_example.txt")
+    P, base, M, Q, q, p, R, idx0, id1, id5, v1, v5 = map(int, row)
+    assert pkg.wheel_start(P, base, M) == (id1, id5)
+
+
+def test_library_table1_equals_oracle_definition():
+    rng = random.Random(17)
+    primes = oracle.simple_primes(3000).tolist()[2:]  # >= 5
+    primes += [65537, 1000003, 31622777, 2147483647, 4294967291]
+    n = 0
+    for P in primes:
+        for _ in range(12):
+            base = 6 * rng.randrange(0, 10 ** 13)
+            if rng.random() < 0.3:  # segments just below P^2, where M = P^2
+                base = max(0, P * P - 6 * rng.randrange(1, 10 ** 6)) // 6 * 6
+            M = max(base, rng.choice([base, base + rng.randrange(1, 6 * P + 7), P * P]))
+            if M - base >= 2 ** 40:
+                M = base + rng.randrange(0, 6 * P)
+            M = max(M, 1)
+            got = pkg.wheel_start(P, base, M)
+            want = (wheel.first_multiple_index(P, base, M, 1),
+                    wheel.first_multiple_index(P, base, M, 5))
+            assert got == want, (P, base, M)
+            n += 1
+    # exhaustive small corner: every M in a window around P^2 and base
+    for P in (5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43):
+        for base in (0, 6, 12000, 6 * 10 ** 15):
+            for M in range(max(1, base), base + 8 * P):
+                assert pkg.wheel_start(P, base, M) == (
+                    wheel.first_multiple_index(P, base, M, 1),
+                    wheel.first_multiple_index(P, base, M, 5)), (P, base, M)
+                n += 1
+    assert n > 5000
+
+
+def test_wheel_start_rejects_bad_input():
+    with pytest.raises(pkg.SieveError):
+        pkg.wheel_start(9, 0, 10)   # 9 = 3 mod 6 is not a wheel prime
+    with pytest.raises(pkg.SieveError):
+        pkg.wheel_start(7, 5, 10)   # base not a multiple of 6
+
+
+@pytest.mark.parametrize("seg", [8192, 65536, 131072, 163840])
+def test_plan_covers_every_wheel_value_once(seg):
+    rng = random.Random(seg)
+    pw = seg // 8
+    per_tile = 192 * pw
+    cases = [(0, 0), (0, 1), (0, 2), (2, 5), (5, 6), (0, 10 ** 7 + 1), (10 ** 12, 10 ** 12 + 10 ** 10)]
+    cases += [(a, a + rng.randrange(0, 4 * per_tile)) for a in
+              (rng.randrange(0, 10 ** 15) for _ in range(200))]
+    for lo, hi in cases:
+        ntiles, base, last = pkg.plan_range(lo, hi, seg)
+        assert base % 6 == 0 and base <= lo < base + 6
+        # the tiles span [base, base + 192 * words), where words counts A_one words
+        words = (ntiles - 1) * pw + last if ntiles else 0
+        end = base + 192 * words
+        vals_lo = [v for v in range(lo, min(hi, lo + 12)) if v % 6 in (1, 5)]
+        vals_hi = [v for v in range(max(lo, hi - 12), hi) if v % 6 in (1, 5)]
+        for v in vals_lo + vals_hi:
+            assert base <= v < end, (lo, hi, v)
+        if ntiles:
+            assert 1 <= last <= pw
+            assert end - 192 < hi or hi <= base + 1  # no whole word beyond hi
+        else:
+            assert not [v for v in range(lo, hi) if v % 6 in (1, 5) and v > 1]
+
+
+def test_list_bound_is_an_upper_bound():
+    rng = random.Random(2)
+    cases = [(0, 0), (0, 1), (0, 2), (0, 3), (0, 4), (2, 3), (0, 100), (0, 10 ** 6),
+             (10 ** 9, 10 ** 9 + 1000)]
+    cases += [(a, a + rng.randrange(0, 200000)) for a in (rng.randrange(0, 10 ** 12) for _ in range(60))]
+    for lo, hi in cases:
+        c = oracle.count(lo, hi)
+        b = pkg.list_bound(lo, hi)
+        assert b >= c, (lo, hi, b, c)
+        if hi - lo > 10 ** 5:
+            assert b <= 6 * c + 100  # not vacuous (2y/ln y vs y/ln x)
