@@ -85,7 +85,7 @@ def main() -> int:
     ap.add_argument("--split-hits", type=int, default=0)
     ap.add_argument("--presieve-groups", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=10 ** 10,
+    ap.add_argument("--cpu-sample", type=int, default=10 ** 11,
                     help="integers of the oracle's timed slice (the top of the range)")
     args = ap.parse_args()
 

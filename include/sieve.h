@@ -62,7 +62,8 @@ typedef struct sieve_ctx sieve_ctx;
  * Tuning parameters (the paper's inputs t, N, S of Fig. 4 become workgroup
  * size, range and segment bytes).  Zero in any field selects the default.
  *   segment_bytes    LDS bytes per tile for the two bit planes together;
- *                    a multiple of 4096 in [8192, device LDS limit].  A tile
+ *                    a multiple of 4096 in [8192, 159744] (156 KiB, leaving
+ *                    room for the kernel's static LDS in 160 KiB).  A tile
  *                    covers 24 * segment_bytes consecutive integers.
  *   block_threads    threads per workgroup: 256, 512 or 1024.
  *   presieve_groups  number of repeating-pattern groups used to initialise

@@ -773,8 +773,9 @@ int sieve_create(sieve_ctx **out, int device, const sieve_params *p)
         return SIEVE_E_NOMEM;
     c->device = device;
     c->cus = prop.multiProcessorCount;
-    // CDNA4 gives a workgroup up to 160 KiB of LDS.
-    c->lds_max = 160 * 1024;
+    // CDNA4 gives a workgroup up to 160 KiB of LDS; the sieve kernel's own
+    // static LDS (tile bookkeeping, under 1 KiB) comes out of the same budget.
+    c->lds_max = 156 * 1024;
     sieve_params q;
     memset(&q, 0, sizeof q);
     if (p)

@@ -244,9 +244,11 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
             uint32_t p1 = 0, p5 = 0;
             if (w < nwords) {
                 uint32_t c1 = pl1[w], c5 = pl5[w];
-                if (w == 0 && B == 0) {
-                    c1 &= ~a.restore1;  // the presieved primes themselves
-                    c5 &= ~a.restore5;
+                if (w == 0 && B < 62) {
+                    // The presieved primes themselves (5..61) lie in word 0
+                    // of any tile based below 62: the patterns marked them.
+                    c1 &= ~(a.restore1 >> (B / 6));
+                    c5 &= ~(a.restore5 >> (B / 6));
                 }
                 if (w == 0) {
                     c1 |= head1;

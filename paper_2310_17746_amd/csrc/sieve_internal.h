@@ -86,7 +86,7 @@ struct SieveArgs {
     const uint2 *ps_tab;
     PsGroup groups[kMaxGroups];
     uint32_t ngroups;
-    uint32_t restore1, restore5;  // word-0 bits of presieved primes (tile base 0)
+    uint32_t restore1, restore5;  // bits of the presieved primes in word 0 of a tile based at 0
     uint32_t pw;                  // plane words per tile
     unsigned long long *bitmap;   // list scratch (u64 words)
     uint32_t *chunk_counts;       // per chunk prime count

@@ -50,9 +50,10 @@ def test_count_tiny_ranges_exhaustive(sv):
         for b in range(a, N + 1):
             lo.append(a)
             hi.append(b)
-    got = sv.count_batch(lo, hi)
-    want = pref[np.array(hi)] - pref[np.array(lo)]
-    assert np.array_equal(got.astype(np.int64), want.astype(np.int64))
+    got = sv.count_batch(lo, hi).astype(np.int64)
+    want = (pref[np.array(hi)] - pref[np.array(lo)]).astype(np.int64)
+    bad = np.nonzero(got != want)[0]
+    assert len(bad) == 0, [(lo[i], hi[i], int(got[i]), int(want[i])) for i in bad[:10]]
     for a, b in [(0, 0), (0, 2), (0, 3), (0, 4), (2, 3), (3, 4), (4, 5), (5, 6), (1, 2), (0, 8)]:
         assert sv.count(a, b) == int(pref[b] - pref[a]), (a, b)
 
@@ -190,7 +191,7 @@ def test_error_paths(sv):
     dict(segment_bytes=8192, block_threads=256),
     dict(segment_bytes=32768, block_threads=1024, presieve_groups=1),
     dict(segment_bytes=131072, block_threads=1024),
-    dict(segment_bytes=163840, block_threads=512, split_hits=64),
+    dict(segment_bytes=159744, block_threads=512, split_hits=64),
     dict(segment_bytes=65536, block_threads=512, presieve_groups=pkg.PRESIEVE_NONE),
     dict(segment_bytes=49152, block_threads=256, presieve_groups=3, split_hits=2048),
 ])
