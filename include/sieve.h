@@ -174,7 +174,8 @@ uint64_t sieve_list_bound(uint64_t lo, uint64_t hi);
  * whose index 0 stands for the values base + 1 and base + 5 (base a
  * multiple of 6) and a first value M >= 1, *id1 and *id5 receive the indices
  * in A_one / A_five of the first multiple of p that is >= M.  Requires
- * base <= M < base + 2^40 (M lies in or near the segment) and p < 2^32.
+ * base <= M < base + 2^22 (M lies within one tile of the base, as in the
+ * kernels) and p < 2^32; otherwise SIEVE_E_INVAL.
  * Host-only, no device work.
  */
 int sieve_wheel_start(uint64_t p, uint64_t base, uint64_t M, int64_t *id1, int64_t *id5);

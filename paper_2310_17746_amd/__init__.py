@@ -19,7 +19,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Sieve", "SieveError", "Params", "list_bound", "wheel_start", "plan_range",
+__all__ = ["Sieve", "SieveError", "Params", "list_bound", "wheel_start", "plan_range", "probe_lds",
            "lib_path", "load_library", "SIEVE_OK", "SIEVE_E_CAPACITY"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -93,6 +93,8 @@ def load_library():
         "sieve_set_timing": (ctypes.c_int, [_p, ctypes.c_int]),
         "sieve_get_timing": (ctypes.c_int, [_p, ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_u64)]),
+        "sieve_probe_lds": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
         "sieve_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "sieve_last_error": (ctypes.c_int, [_p]),
     }
@@ -128,6 +130,20 @@ def plan_range(lo: int, hi: int, segment_bytes: int) -> tuple[int, int, int]:
     _check(load_library().sieve_plan_range(lo, hi, segment_bytes, ctypes.byref(n), ctypes.byref(b),
                                            ctypes.byref(w)), "sieve_plan_range")
     return n.value, b.value, w.value
+
+
+PROBE_MODES = {"or_linear": 0, "or_random": 1, "or_even": 2, "or_same": 3, "write_linear": 4,
+               "write_random": 5, "write8_random": 6, "read_random": 7}
+
+
+def probe_lds(mode: str, iters: int = 4096, wg_per_cu: int = 1, device: int = 0) -> tuple[float, float]:
+    """LDS probe (include/sieve_probe.h): (lane operations per second, kernel ms)."""
+    ops, ms = ctypes.c_double(), ctypes.c_double()
+    code = load_library().sieve_probe_lds(device, PROBE_MODES[mode], iters, wg_per_cu,
+                                          ctypes.byref(ops), ctypes.byref(ms))
+    if code != 0:
+        raise SieveError(code, "sieve_probe_lds")
+    return ops.value, ms.value
 
 
 def _torch():

@@ -116,8 +116,7 @@ struct sieve_ctx {
     // Resident base primes (>= 5) and derived constants.
     uint64_t limit = 0;
     std::vector<uint32_t> h_primes;
-    DevBuf<uint2> d_prm;
-    DevBuf<uint64_t> d_rcp;
+    DevBuf<PrimeConst> d_prm;
     DevBuf<uint32_t> d_pidx;
     DevBuf<uint2> d_items;
     DevBuf<uint32_t> d_item_prefix;
@@ -141,6 +140,7 @@ struct sieve_ctx {
     size_t h_blob_n = 0;
     unsigned long long *h_counts = nullptr;  // pinned
     int32_t *h_status = nullptr;             // pinned
+    unsigned long long *h_flag = nullptr;    // pinned copy of the kernels' error flag
     uint64_t cap_ranges = 0, cap_list = 0, cap_chunks = 0;
 
     // Graph of the job kernels; valid while gen == graph_gen.
@@ -205,22 +205,30 @@ int validate_params(const sieve_params &p, uint32_t lds_max)
     return SIEVE_OK;
 }
 
-// Builds the presieve tables for the first `ng` groups and uploads them.
+// Builds the presieve tables and uploads them.  The first `ng` groups hold
+// their patterns; the rest get an all-zero table (period 64) so that the
+// kernel applies every group unconditionally.
 int build_presieve(sieve_ctx *c, uint32_t ng)
 {
     std::vector<uint2> tab;
     c->ngroups = ng;
     c->restore1 = c->restore5 = 0;
-    for (uint32_t g = 0; g < ng; ++g) {
+    for (uint32_t g = 0; g < (uint32_t)kMaxGroups; ++g) {
+        const bool on = g < ng;
         uint32_t P = 1;
-        for (int i = 0; i < 4 && kGroupPrimes[g][i]; ++i)
-            P *= kGroupPrimes[g][i];
+        if (on)
+            for (int i = 0; i < 4 && kGroupPrimes[g][i]; ++i)
+                P *= kGroupPrimes[g][i];
+        else
+            P = 64;
         const uint32_t nw = (P + 64 + 31) / 32 + 1;
         PsGroup &G = c->groups[g];
         G.period = P;
         G.offset = (uint32_t)tab.size();
         G.step = (32u * c->prm.block_threads) % P;
         tab.resize(tab.size() + nw, make_uint2(0, 0));
+        if (!on)
+            continue;
         for (uint32_t t = 0; t < nw * 32; ++t) {
             const uint64_t tt = t % P;
             const uint64_t v1 = 6 * tt + 1, v5 = 6 * tt + 5;
@@ -242,8 +250,6 @@ int build_presieve(sieve_ctx *c, uint32_t ng)
                 c->restore5 |= 1u << ((p - 5) / 6);
         }
     }
-    if (tab.empty())
-        tab.push_back(make_uint2(0, 0));
     if (!c->d_pstab.reserve(tab.size()))
         return SIEVE_E_NOMEM;
     return hip_status(hipMemcpy(c->d_pstab.p, tab.data(), tab.size() * sizeof(uint2), hipMemcpyHostToDevice));
@@ -255,11 +261,10 @@ int install_primes(sieve_ctx *c, uint64_t limit)
 {
     const std::vector<uint32_t> &P = c->h_primes;
     const size_t n = P.size();
-    std::vector<uint2> prm(std::max<size_t>(n, 1), make_uint2(0, 0));
-    std::vector<uint64_t> rcp(std::max<size_t>(n, 1), 0);
+    std::vector<PrimeConst> prm(std::max<size_t>(n, 1), PrimeConst{0, 0, 0, 0});
     for (size_t k = 0; k < n; ++k) {
-        prm[k] = make_uint2(P[k], P[k] / 6);
-        rcp[k] = UINT64_MAX / P[k];
+        const uint64_t m = UINT64_MAX / P[k];
+        prm[k] = PrimeConst{P[k], P[k] / 6, (uint32_t)m, (uint32_t)(m >> 32)};
     }
     const size_t np = limit / 64 + 2;
     std::vector<uint32_t> pidx(np);
@@ -295,13 +300,11 @@ int install_primes(sieve_ctx *c, uint64_t limit)
     }
     if (items.empty())
         items.push_back(make_uint2(0, 0));
-    if (!c->d_prm.reserve(prm.size(), &c->gen) || !c->d_rcp.reserve(rcp.size(), &c->gen) ||
+    if (!c->d_prm.reserve(prm.size(), &c->gen) ||
         !c->d_pidx.reserve(pidx.size(), &c->gen) || !c->d_items.reserve(items.size(), &c->gen) ||
         !c->d_item_prefix.reserve(prefix.size(), &c->gen))
         return SIEVE_E_NOMEM;
-    hipError_t e = hipMemcpy(c->d_prm.p, prm.data(), prm.size() * sizeof(uint2), hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipMemcpy(c->d_rcp.p, rcp.data(), rcp.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
+    hipError_t e = hipMemcpy(c->d_prm.p, prm.data(), prm.size() * sizeof(PrimeConst), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(c->d_pidx.p, pidx.data(), pidx.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess)
@@ -453,6 +456,11 @@ int ensure_capacity(sieve_ctx *c, uint64_t nranges, uint64_t nlist, uint64_t nch
     if (!c->d_counters.p) {
         if (!c->d_counters.reserve(kNumCounters))
             return SIEVE_E_NOMEM;
+        if (!c->h_flag && hipHostMalloc((void **)&c->h_flag, sizeof(unsigned long long), hipHostMallocDefault) !=
+                              hipSuccess) {
+            (void)hipGetLastError();
+            return SIEVE_E_NOMEM;
+        }
         changed = true;
     }
     if (changed)
@@ -478,7 +486,6 @@ hipError_t enqueue_kernels(sieve_ctx *c, hipStream_t s, bool timed)
     a.counters = c->d_counters.p;
     a.counts = c->d_counts.p;
     a.prm = c->d_prm.p;
-    a.rcp = c->d_rcp.p;
     a.pidx = c->d_pidx.p;
     a.pidx_len = (uint32_t)(c->limit / 64 + 2);
     a.nprimes = (uint32_t)c->h_primes.size();
@@ -614,8 +621,14 @@ int run_job(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, co
         if (e != hipSuccess)
             return hip_status(e);
     }
+    e = hipMemcpyAsync(c->h_flag, c->d_counters.p + kErrorFlag, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                       s);
+    if (e != hipSuccess)
+        return hip_status(e);
     if ((e = hipStreamSynchronize(s)) != hipSuccess)
         return hip_status(e);
+    if (*c->h_flag)
+        return SIEVE_E_DEVICE;  // a kernel refused to run (see its error flag)
     if (c->timing && !use_graph) {
         float a = 0, b = 0;
         if (hipEventElapsedTime(&a, c->ev[0], c->ev[1]) == hipSuccess &&
@@ -682,7 +695,6 @@ void destroy_ctx(sieve_ctx *c)
     if (c->graph_src)
         (void)hipGraphDestroy(c->graph_src);
     c->d_prm.release();
-    c->d_rcp.release();
     c->d_pidx.release();
     c->d_items.release();
     c->d_item_prefix.release();
@@ -700,6 +712,8 @@ void destroy_ctx(sieve_ctx *c)
         (void)hipHostFree(c->h_counts);
     if (c->h_status)
         (void)hipHostFree(c->h_status);
+    if (c->h_flag)
+        (void)hipHostFree(c->h_flag);
     for (auto &ev : c->ev)
         if (ev)
             (void)hipEventDestroy(ev);
@@ -952,10 +966,10 @@ uint64_t sieve_list_bound(uint64_t lo, uint64_t hi)
 int sieve_wheel_start(uint64_t p, uint64_t base, uint64_t M, int64_t *id1, int64_t *id5)
 {
     if (!id1 || !id5 || p < 5 || (p % 6 != 1 && p % 6 != 5) || base % 6 || M < 1 || M < base ||
-        M - base >= (1ull << 40) || p >= (1ull << 32))
+        M - base >= (1ull << 22) || p >= (1ull << 32))
         return SIEVE_E_INVAL;
-    int64_t a, b;
-    wheel_start(p, p / 6, UINT64_MAX / p, base, M, a, b);
+    uint32_t a, b;
+    wheel_start((uint32_t)p, (uint32_t)(p / 6), UINT64_MAX / p, base, M, p < 0x80000000ull, a, b);
     *id1 = a;
     *id5 = b;
     return SIEVE_OK;

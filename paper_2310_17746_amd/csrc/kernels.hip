@@ -63,57 +63,80 @@ __device__ inline uint64_t spread32(uint32_t x)
     return v;
 }
 
-__device__ inline void lds_set(uint32_t *pl, uint32_t i)
+// The two planes live interleaved at LDS byte address 0: word w of A_one at
+// byte 8w, word w of A_five at byte 8w + 4.  Marks address LDS through this
+// computed byte address (the kernel checks that its dynamic LDS starts at 0).
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
+__device__ __forceinline__ void lds_or(uint32_t byte_addr, uint32_t mask)
 {
-    atomicOr(&pl[i >> 5], 1u << (i & 31));
+    __atomic_fetch_or((lds_u32 *)(size_t)byte_addr, mask, __ATOMIC_RELAXED);
 }
 
-// Clears (sets the composite bit of) start, start + step, ... below nbits.
-// The paper strides by P indices in each array (Sec. 3: adding P to the
-// index adds 6P to the value and keeps the residue mod 6).
-__device__ inline void mark_plane(uint32_t *pl, int64_t start, uint32_t step, uint32_t nbits)
+// Sets the composite bits start, start + step, ... below nbits of one plane
+// (ROFF = 0 for A_one, 4 for A_five).  The paper strides by P indices in
+// each array (Sec. 3: adding P to the index adds 6P to the value and keeps
+// the residue mod 6).
+template <uint32_t ROFF>
+__device__ __forceinline__ void mark_plane(uint64_t start, uint32_t step, uint32_t nbits)
 {
-    if (start >= (int64_t)nbits)
+    if (start >= nbits)
         return;
     uint32_t i = (uint32_t)start;
     if (step < (nbits >> 2)) {
-        for (; i + 3 * step < nbits; i += 4 * step) {
-            lds_set(pl, i);
-            lds_set(pl, i + step);
-            lds_set(pl, i + 2 * step);
-            lds_set(pl, i + 3 * step);
+        const uint32_t lim = nbits - 3 * step;  // i < lim keeps i + 3*step < nbits
+        while (i < lim) {
+            // Keep one induction variable in a register (an empty asm operand
+            // stops the compiler from splitting it into several).
+            asm volatile("" : "+v"(i));
+            const uint32_t i1 = i + step, i2 = i1 + step, i3 = i2 + step;
+            lds_or(((i >> 2) & ~7u) + ROFF, 1u << (i & 31));
+            lds_or(((i1 >> 2) & ~7u) + ROFF, 1u << (i1 & 31));
+            lds_or(((i2 >> 2) & ~7u) + ROFF, 1u << (i2 & 31));
+            lds_or(((i3 >> 2) & ~7u) + ROFF, 1u << (i3 & 31));
+            i = i3 + step;
         }
     }
     for (; i < nbits; i += step)
-        lds_set(pl, i);
+        lds_or(((i >> 2) & ~7u) + ROFF, 1u << (i & 31));
 }
 
 }  // namespace
+
+// Bookkeeping of one tile, kept in LDS after the two planes so that the
+// planes start at LDS address 0 (a mark's address is then (i >> 3) & ~3).
+struct TileShared {
+    unsigned long long tile;
+    uint32_t range;
+    uint32_t nact;
+    uint32_t psoff[kMaxGroups];
+    uint32_t red[1024 / 64];
+    uint32_t chunk[64];
+};
 
 template <int NT>
 __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
 {
     extern __shared__ uint32_t lds[];
-    __shared__ unsigned long long s_tile;
-    __shared__ uint32_t s_range;
-    __shared__ uint32_t s_nact;
-    __shared__ uint32_t s_psoff[kMaxGroups];
-    __shared__ uint32_t s_red[NT / kWave];
-    __shared__ uint32_t s_chunk[64];
-
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1);
     const uint32_t wave = tid / kWave;
     const uint32_t pw = a.pw;
-    uint32_t *pl1 = lds;
-    uint32_t *pl5 = lds + pw;
+    uint2 *planes = reinterpret_cast<uint2 *>(lds);  // {A_one, A_five} word pairs
+    TileShared &sh = *reinterpret_cast<TileShared *>(lds + 2 * pw);
     const uint64_t ntiles = a.job->ntiles;
     const uint32_t nranges = a.job->nranges;
+    if ((uint32_t)(size_t)(__attribute__((address_space(3))) void *)lds != 0) {
+        // Marks assume the planes at LDS address 0; report and do nothing.
+        if (tid == 0 && blockIdx.x == 0)
+            atomicOr(&a.counters[kErrorFlag], 1ull);
+        return;
+    }
 
     for (;;) {
         if (tid == 0) {
             const unsigned long long t = atomicAdd(&a.counters[kTileCounter], 1ull);
-            s_tile = t;
+            sh.tile = t;
             if (t < ntiles) {
                 // Last range whose first tile is <= t.
                 uint32_t lo = 0, hi = nranges;
@@ -124,7 +147,7 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
                     else
                         hi = mid;
                 }
-                s_range = lo;
+                sh.range = lo;
                 const RangeDesc &d = a.ranges[lo];
                 const uint64_t k = t - d.tile0;
                 const uint32_t nw = (k + 1 == d.ntiles) ? d.last_words : pw;
@@ -135,16 +158,17 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
                 uint64_t s = (isqrt_dev(tend - 1) + 63) / 64;
                 if (s >= a.pidx_len)
                     s = a.pidx_len - 1;
-                s_nact = a.pidx[s];
+                sh.nact = a.pidx[s];
             }
         }
         if (tid < 64)
-            s_chunk[tid] = 0;
+            sh.chunk[tid] = 0;
         __syncthreads();
-        const unsigned long long t = s_tile;
+        const unsigned long long t = sh.tile;
         if (t >= ntiles)
             break;
-        const RangeDesc &d = a.ranges[s_range];
+        const uint32_t rix = sh.range;
+        const RangeDesc &d = a.ranges[rix];
         const uint64_t k = t - d.tile0;
         const bool first = (k == 0);
         const bool last = (k + 1 == d.ntiles);
@@ -154,44 +178,47 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
         const uint32_t nbits = nwords * 32;
 
         // ---- presieve init: OR of the repeating composite patterns -------
-        if (tid < a.ngroups)
-            s_psoff[tid] = (uint32_t)((B / 6) % a.groups[tid].period);
+        if (tid < kMaxGroups)
+            sh.psoff[tid] = (uint32_t)((B / 6) % a.groups[tid].period);
         __syncthreads();
         {
+            // Every group is always applied; a disabled group has an all-zero
+            // table, so the loop has no data-dependent branches.
             uint32_t o[kMaxGroups];
 #pragma unroll
             for (int g = 0; g < kMaxGroups; ++g)
-                if (g < (int)a.ngroups)
-                    o[g] = (s_psoff[g] + 32u * tid) % a.groups[g].period;
+                o[g] = (sh.psoff[g] + 32u * tid) % a.groups[g].period;
             for (uint32_t w = tid; w < nwords; w += NT) {
-                uint32_t c1 = 0, c5 = 0;
+                uint2 x[kMaxGroups], y[kMaxGroups];
 #pragma unroll
                 for (int g = 0; g < kMaxGroups; ++g) {
-                    if (g < (int)a.ngroups) {
-                        const uint2 *tb = a.ps_tab + a.groups[g].offset + (o[g] >> 5);
-                        const uint2 x = tb[0];
-                        const uint2 y = tb[1];
-                        const uint32_t sh = o[g] & 31;
-                        c1 |= __builtin_amdgcn_alignbit(y.x, x.x, sh);
-                        c5 |= __builtin_amdgcn_alignbit(y.y, x.y, sh);
-                        o[g] += a.groups[g].step;
-                        if (o[g] >= a.groups[g].period)
-                            o[g] -= a.groups[g].period;
-                    }
+                    const uint2 *tb = a.ps_tab + a.groups[g].offset + (o[g] >> 5);
+                    x[g] = tb[0];
+                    y[g] = tb[1];
                 }
-                pl1[w] = c1;
-                pl5[w] = c5;
+                uint2 c = make_uint2(0, 0);
+#pragma unroll
+                for (int g = 0; g < kMaxGroups; ++g) {
+                    const uint32_t sft = o[g] & 31;
+                    c.x |= __builtin_amdgcn_alignbit(y[g].x, x[g].x, sft);
+                    c.y |= __builtin_amdgcn_alignbit(y[g].y, x[g].y, sft);
+                    o[g] += a.groups[g].step;
+                    o[g] = o[g] >= a.groups[g].period ? o[g] - a.groups[g].period : o[g];
+                }
+                planes[w] = c;
             }
         }
         __syncthreads();
 
         // ---- marking: Table 1 starts, stride P in each plane -------------
         {
-            const uint32_t n_act = s_nact;
+            const uint32_t n_act = sh.nact;
             const uint32_t ks = n_act < a.k_split ? n_act : a.k_split;
             const uint32_t n_items = ks > a.first_mark ? a.item_prefix[ks - a.first_mark] : 0;
             const uint32_t n_rest = n_act > a.k_split ? n_act - a.k_split : 0;
             const uint32_t n_work = n_items + n_rest;
+            // Every active prime is below 2^31 when the tile ends below 2^62.
+            const bool narrow = tend <= (1ull << 62);
             for (uint32_t v = tid; v < n_work; v += NT) {
                 uint32_t kp, j, g;
                 if (v < n_items) {
@@ -204,17 +231,17 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
                     j = 0;
                     g = 1;
                 }
-                const uint2 pr = a.prm[kp];
-                const uint64_t P = pr.x;
-                const uint64_t P2 = P * P;
+                const PrimeConst pc = a.prm[kp];
+                const uint64_t P2 = (uint64_t)pc.p * pc.p;
                 const uint64_t M = P2 > B ? P2 : B;
                 if (M >= tend)
                     continue;
-                int64_t id1, id5;
-                wheel_start(P, pr.y, a.rcp[kp], B, M, id1, id5);
-                const uint32_t step = g * pr.x;
-                mark_plane(pl1, id1 + (int64_t)j * (int64_t)P, step, nbits);
-                mark_plane(pl5, id5 + (int64_t)j * (int64_t)P, step, nbits);
+                uint32_t id1, id5;
+                wheel_start(pc.p, pc.r, ((uint64_t)pc.m_hi << 32) | pc.m_lo, B, M, narrow, id1, id5);
+                const uint32_t step = g * pc.p;
+                const uint32_t off = j * pc.p;
+                mark_plane<0>((uint64_t)id1 + off, step, nbits);
+                mark_plane<4>((uint64_t)id5 + off, step, nbits);
             }
         }
         __syncthreads();
@@ -243,7 +270,8 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
         for (uint32_t w = tid; w < nw_pad; w += NT) {
             uint32_t p1 = 0, p5 = 0;
             if (w < nwords) {
-                uint32_t c1 = pl1[w], c5 = pl5[w];
+                const uint2 cw = planes[w];
+                uint32_t c1 = cw.x, c5 = cw.y;
                 if (w == 0 && B < 62) {
                     // The presieved primes themselves (5..61) lie in word 0
                     // of any tile based below 62: the patterns marked them.
@@ -266,7 +294,7 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
                 a.bitmap[wbase + w] = spread32(p1) | (spread32(p5) << 1);
                 const uint32_t ws = wave_sum(c);
                 if (lane == 0)
-                    atomicAdd(&s_chunk[w / kChunkWords], ws);
+                    atomicAdd(&sh.chunk[w / kChunkWords], ws);
             } else {
                 cnt += c;
             }
@@ -276,17 +304,17 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
             const uint32_t nch = nw_pad / kChunkWords;
             const uint64_t cbase = d.chunk0 + k * (pw / kChunkWords);
             if (tid < nch)
-                a.chunk_counts[cbase + tid] = s_chunk[tid];
+                a.chunk_counts[cbase + tid] = sh.chunk[tid];
         } else {
             cnt = wave_sum(cnt);
             if (lane == 0)
-                s_red[wave] = cnt;
+                sh.red[wave] = cnt;
             __syncthreads();
             if (tid == 0) {
                 uint32_t tot = 0;
                 for (uint32_t i = 0; i < NT / kWave; ++i)
-                    tot += s_red[i];
-                atomicAdd(&a.counts[s_range], (unsigned long long)tot);
+                    tot += sh.red[i];
+                atomicAdd(&a.counts[rix], (unsigned long long)tot);
             }
         }
         __syncthreads();
@@ -446,16 +474,17 @@ __global__ void k_zero(const JobHeader *job, unsigned long long *counters, unsig
 // ---------------------------------------------------------------------------
 // Host-side launch helpers (called from the runtime in api.hip).
 // ---------------------------------------------------------------------------
-hipError_t set_sieve_lds_limit(uint32_t bytes)
+hipError_t set_sieve_lds_limit(uint32_t segment_bytes)
 {
+    const int bytes = (int)(segment_bytes + sizeof(TileShared));
     hipError_t e;
-    e = hipFuncSetAttribute((const void *)k_sieve<256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    e = hipFuncSetAttribute((const void *)k_sieve<256>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess)
         return e;
-    e = hipFuncSetAttribute((const void *)k_sieve<512>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    e = hipFuncSetAttribute((const void *)k_sieve<512>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess)
         return e;
-    return hipFuncSetAttribute((const void *)k_sieve<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    return hipFuncSetAttribute((const void *)k_sieve<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 hipError_t launch_zero(const JobHeader *job, unsigned long long *counters, unsigned long long *counts,
@@ -467,7 +496,7 @@ hipError_t launch_zero(const JobHeader *job, unsigned long long *counters, unsig
 
 hipError_t launch_sieve(const SieveArgs &a, uint32_t nt, uint32_t grid, hipStream_t s)
 {
-    const size_t lds = (size_t)a.pw * 8;
+    const size_t lds = (size_t)a.pw * 8 + sizeof(TileShared);  // planes, then bookkeeping
     switch (nt) {
     case 256:
         hipLaunchKernelGGL(k_sieve<256>, dim3(grid), dim3(256), lds, s, a);

@@ -1,10 +1,11 @@
 // Internal layout shared by the HIP kernels and the host runtime of libsieve.
 //
 // Value layout (Sec. 2.1, Fig. 2): a tile with value base B (a multiple of
-// 6) holds two bit planes of PW 32-bit words each in LDS.  Bit i of plane
-// A_r (r = 1 or 5) stands for the value B + 6*i + r.  One plane word covers
-// 192 consecutive integers; a tile covers 192 * PW integers.  In LDS a set
-// bit means "composite / excluded" so that marking is a single LDS OR.
+// 6) holds two bit planes of PW 32-bit words each in LDS, interleaved word by
+// word (A_one word w at byte 8w, A_five word w at byte 8w + 4).  Bit i of
+// plane A_r (r = 1 or 5) stands for the value B + 6*i + r.  One plane word
+// covers 192 consecutive integers; a tile covers 192 * PW integers.  In LDS a
+// set bit means "composite / excluded" so that marking is a single LDS OR.
 //
 // List output goes through a value-ordered bitmap in HBM: plane word w of
 // A_one and A_five are interleaved into one 64-bit word whose bit 2i is
@@ -16,6 +17,8 @@
 #include <stdint.h>
 
 #include <hip/hip_runtime.h>
+
+#include "wheel.h"
 
 namespace sieve {
 
@@ -54,7 +57,7 @@ struct JobHeader {
 };
 
 // Counters zeroed at the start of every job.
-enum Counter { kTileCounter = 0, kChunkCounter = 1, kNumCounters = 4 };
+enum Counter { kTileCounter = 0, kChunkCounter = 1, kErrorFlag = 2, kNumCounters = 4 };
 
 // A presieve pattern group: primes whose product is `period`.  Its table
 // holds period + 64 bits per plane (bit t stands for 6t + r, set when some
@@ -74,8 +77,7 @@ struct SieveArgs {
     const RangeDesc *ranges;
     unsigned long long *counters;
     unsigned long long *counts;   // per range
-    const uint2 *prm;             // {p, p / 6} for every resident prime >= 5, ascending
-    const uint64_t *rcp;          // floor((2^64 - 1) / p)
+    const PrimeConst *prm;        // every resident prime >= 5, ascending
     const uint32_t *pidx;         // pidx[s] = number of resident primes <= 64 * s
     uint32_t pidx_len;
     uint32_t nprimes;
@@ -84,7 +86,7 @@ struct SieveArgs {
     const uint2 *items;           // {prime index, (j << 16) | g}
     const uint32_t *item_prefix;  // items before prime first_mark + i
     const uint2 *ps_tab;
-    PsGroup groups[kMaxGroups];
+    PsGroup groups[kMaxGroups];       // all applied; disabled ones are all-zero
     uint32_t ngroups;
     uint32_t restore1, restore5;  // bits of the presieved primes in word 0 of a tile based at 0
     uint32_t pw;                  // plane words per tile

@@ -11,11 +11,15 @@
 // M is max(B, P*P): marking starts at the square (Sec. 1.1, Sec. 2.4), which
 // also keeps a segment that holds P itself from clearing it.
 //
-// The division by P uses a per-prime reciprocal m = floor((2^64 - 1) / P):
-// for any 64-bit x, mulhi64(x, m) is floor(x / P) or one less (m is below
-// 2^64 / P by less than 1, so x * m / 2^64 > x / P - 1), and one conditional
-// subtraction of P from the remainder corrects it (Granlund and Montgomery,
-// PLDI 1994, division by invariant integers using multiplication).
+// Arithmetic.  The one wide step is x mod P for the 64-bit x = M - 1; it uses
+// a per-prime reciprocal m = floor((2^64 - 1) / P): mulhi64(x, m) is
+// floor(x / P) or one less (m is below 2^64 / P by less than 1, so
+// x * m / 2^64 > x / P - 1), and one conditional subtraction of P corrects it
+// (Granlund and Montgomery, PLDI 1994, division by invariant integers using
+// multiplication).  Everything after it fits in 32 bits: d = Q - B lies in
+// [-P, 2^22) for a tile, so d + 6(R + 1) (> P) is non-negative and below
+// 2^32 for every P < 3.1e9, and floor division of that biased value by 6
+// gives idx0 + R + 1 and q = Q mod 6 without signed 64-bit division.
 #pragma once
 
 #include <stdint.h>
@@ -24,22 +28,37 @@
 
 namespace sieve {
 
-// Table 1 as printed in the paper.  Entry [p == 5][q] = {k1, c1, k5, c5}:
-// id_1 = idx0 + k1*R + c1 and id_5 = idx0 + k5*R + c5.  The paper's
-// "k*(R+1) - 1" is stored as (k, k-1) and "k*(R+1)" as (k, k).
-struct Table1Entry {
-    uint8_t k1, c1, k5, c5;
-};
-
-__host__ __device__ constexpr Table1Entry table1(int p5, int q)
+// Table 1 as printed in the paper, one byte per column q = 0..5 (byte q),
+// each byte holding (k - 1) | (c << 3) for id = idx0 + k*R + c.
+// The paper's "k*(R+1) - 1" is (k, k-1) and "k*(R+1)" is (k, k).
+//   p = 1:  id_1: R, 6R+1, 5R+1, 4R+1, 3R+1, 2R+1
+//           id_5: 5R, 4R,   3R,   2R,   R,    6R+1
+//   p = 5:  id_1: 5(R+1)-1, 6(R+1)-1, R+1,      2(R+1),   3(R+1),   4(R+1)
+//           id_5: R,        2(R+1)-1, 3(R+1)-1, 4(R+1)-1, 5(R+1)-1, 6(R+1)-1
+constexpr uint64_t table1_byte(int k, int c) { return (uint64_t)((k - 1) | (c << 3)); }
+constexpr uint64_t table1_row(const int (&kc)[6][2])
 {
-    // Rows p = 1 (p5 == 0) and p = 5 (p5 == 1), columns q = 0..5.
-    constexpr Table1Entry t[2][6] = {
-        {{1, 0, 5, 0}, {6, 1, 4, 0}, {5, 1, 3, 0}, {4, 1, 2, 0}, {3, 1, 1, 0}, {2, 1, 6, 1}},
-        {{5, 4, 1, 0}, {6, 5, 2, 1}, {1, 1, 3, 2}, {2, 2, 4, 3}, {3, 3, 5, 4}, {4, 4, 6, 5}},
-    };
-    return t[p5][q];
+    uint64_t v = 0;
+    for (int q = 0; q < 6; ++q)
+        v |= table1_byte(kc[q][0], kc[q][1]) << (8 * q);
+    return v;
 }
+constexpr int kT1p1[6][2] = {{1, 0}, {6, 1}, {5, 1}, {4, 1}, {3, 1}, {2, 1}};
+constexpr int kT5p1[6][2] = {{5, 0}, {4, 0}, {3, 0}, {2, 0}, {1, 0}, {6, 1}};
+constexpr int kT1p5[6][2] = {{5, 4}, {6, 5}, {1, 1}, {2, 2}, {3, 3}, {4, 4}};
+constexpr int kT5p5[6][2] = {{1, 0}, {2, 1}, {3, 2}, {4, 3}, {5, 4}, {6, 5}};
+constexpr uint64_t kTable1_id1_p1 = table1_row(kT1p1);
+constexpr uint64_t kTable1_id5_p1 = table1_row(kT5p1);
+constexpr uint64_t kTable1_id1_p5 = table1_row(kT1p5);
+constexpr uint64_t kTable1_id5_p5 = table1_row(kT5p5);
+
+// Per-prime constants resident on the device (16 bytes, one load).
+struct PrimeConst {
+    uint32_t p;       // the prime, >= 5
+    uint32_t r;       // floor(p / 6)
+    uint32_t m_lo;    // floor((2^64 - 1) / p), low and high halves
+    uint32_t m_hi;
+};
 
 __host__ __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b)
 {
@@ -50,33 +69,41 @@ __host__ __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b)
 #endif
 }
 
-// x mod P for P >= 2, given m = floor((2^64 - 1) / P).
-__host__ __device__ inline uint64_t mod_invariant(uint64_t x, uint64_t P, uint64_t m)
+// x mod P for 5 <= P < 2^32, given m = floor((2^64 - 1) / P).  `narrow`
+// (P < 2^31) lets the correction run in 32 bits: the remainder before it is
+// below 2P.  Callers pass a value that is uniform across the wavefront.
+__host__ __device__ inline uint32_t mod_invariant(uint64_t x, uint32_t P, uint64_t m, bool narrow)
 {
-    uint64_t r = x - mulhi64(x, m) * P;
-    return r >= P ? r - P : r;
+    const uint64_t q = mulhi64(x, m);  // floor(x / P) or one less
+    if (narrow) {
+        uint32_t r = (uint32_t)x - (uint32_t)q * P;
+        return r >= P ? r - P : r;
+    }
+    uint64_t r = x - q * (uint64_t)P;
+    return (uint32_t)(r >= P ? r - P : r);
 }
 
-// Start indices (relative to base B) of prime P in both planes for first
-// value M >= 1, M >= B.  R = P / 6, m = reciprocal of P.  Both results are
-// >= 0; callers compare them against the plane length.
-__host__ __device__ inline void wheel_start(uint64_t P, uint64_t R, uint64_t m, uint64_t B,
-                                            uint64_t M, int64_t &id1, int64_t &id5)
+// Start indices (relative to base B) of prime P in both planes for a first
+// value M with B <= M < B + 2^22 and M >= 1.  Both results are the true
+// indices (>= 0); callers compare them against the plane length.  `narrow`
+// must be true only when P < 2^31.
+__host__ __device__ inline void wheel_start(uint32_t P, uint32_t R, uint64_t m, uint64_t B, uint64_t M,
+                                            bool narrow, uint32_t &id1, uint32_t &id5)
 {
     const uint64_t x = M - 1;
-    const uint64_t Q = x - mod_invariant(x, P, m);  // greatest multiple of P below M
-    const int64_t d = (int64_t)(Q - B);             // >= -P, may be negative
-    // floor division by 6 and the matching non-negative remainder q = Q mod 6
-    // (B is a multiple of 6, so Q mod 6 = d mod 6).
-    int64_t idx0 = d / 6;
-    int64_t q = d - 6 * idx0;
-    if (q < 0) {
-        q += 6;
-        idx0 -= 1;
-    }
-    const Table1Entry e = table1((P - 6 * R) == 5, (int)q);
-    id1 = idx0 + (int64_t)e.k1 * (int64_t)R + e.c1;
-    id5 = idx0 + (int64_t)e.k5 * (int64_t)R + e.c5;
+    const uint32_t rem = mod_invariant(x, P, m, narrow);  // Q = x - rem, greatest multiple below M
+    // dp = (Q - B) + 6(R + 1), computed mod 2^32 (its true value is in [1, 2^32)).
+    const uint32_t dp = (uint32_t)(x - B) - rem + 6u * (R + 1u);
+    const uint32_t i0 = dp / 6u;       // = idx0 + R + 1
+    const uint32_t q = dp - 6u * i0;   // = Q mod 6
+    const bool p5 = (P - 6u * R) == 5u;
+    const uint64_t t1 = p5 ? kTable1_id1_p5 : kTable1_id1_p1;
+    const uint64_t t5 = p5 ? kTable1_id5_p5 : kTable1_id5_p1;
+    const uint32_t e1 = (uint32_t)(t1 >> (8u * q));
+    const uint32_t e5 = (uint32_t)(t5 >> (8u * q));
+    // id = idx0 + k*R + c = i0 + (k - 1)*R + c - 1
+    id1 = i0 + (e1 & 7u) * R + ((e1 >> 3) & 7u) - 1u;
+    id5 = i0 + (e5 & 7u) * R + ((e5 >> 3) & 7u) - 1u;
 }
 
 }  // namespace sieve

@@ -21,9 +21,13 @@ pkg = pytest.importorskip("paper_2310_17746_amd")
 
 
 def _declared_functions():
-    hdr = open(os.path.join(ROOT, "include", "sieve.h")).read()
-    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
-    return sorted(set(re.findall(r"\b(sieve_[a-z_0-9]+)\s*\(", hdr)))
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in sorted(os.listdir(inc)):
+        if fn.endswith(".h"):
+            hdr = re.sub(r"/\*.*?\*/", "", open(os.path.join(inc, fn)).read(), flags=re.S)
+            names |= set(re.findall(r"\b(sieve_[a-z_0-9]+)\s*\(", hdr))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
@@ -51,8 +55,8 @@ def test_library_table1_equals_oracle_definition():
             if rng.random() < 0.3:  # segments just below P^2, where M = P^2
                 base = max(0, P * P - 6 * rng.randrange(1, 10 ** 6)) // 6 * 6
             M = max(base, rng.choice([base, base + rng.randrange(1, 6 * P + 7), P * P]))
-            if M - base >= 2 ** 40:
-                M = base + rng.randrange(0, 6 * P)
+            if M - base >= 2 ** 22:
+                M = base + rng.randrange(0, 2 ** 22)
             M = max(M, 1)
             got = pkg.wheel_start(P, base, M)
             want = (wheel.first_multiple_index(P, base, M, 1),
@@ -62,7 +66,7 @@ def test_library_table1_equals_oracle_definition():
     # exhaustive small corner: every M in a window around P^2 and base
     for P in (5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43):
         for base in (0, 6, 12000, 6 * 10 ** 15):
-            for M in range(max(1, base), base + 8 * P):
+            for M in range(max(1, base), base + 8 * P):  # all within 2^22 of base
                 assert pkg.wheel_start(P, base, M) == (
                     wheel.first_multiple_index(P, base, M, 1),
                     wheel.first_multiple_index(P, base, M, 5)), (P, base, M)
