@@ -198,6 +198,95 @@ int sieve_plan_range(uint64_t lo, uint64_t hi, uint32_t segment_bytes, uint64_t 
 int sieve_set_timing(sieve_ctx *ctx, int on);
 int sieve_get_timing(const sieve_ctx *ctx, double *sieve_ms, double *post_ms, uint64_t *jobs);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of range queries.
+ *
+ * A server owns a context (no other call may use that context while the
+ * server exists) and runs a scheduler thread.  Requests wait in FIFO order
+ * until a slot is free and, for list requests, their output fits the
+ * server's device output arena (the output-memory budget; a list request
+ * reserves sieve_list_bound(lo, hi) elements).  Every scheduler step runs one
+ * batched job over tile-aligned pieces of all active requests: each active
+ * request gets up to `quantum_tiles` tiles per step (round-robin), at most
+ * `step_tiles` tiles per step in total, so a long request shares the device
+ * with short ones.  A request completes when its last piece finishes; its
+ * result is identical to a stand-alone sieve_count / sieve_list of the range.
+ * Base primes grow on demand.  Every server call is thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef struct sieve_server sieve_server;
+
+typedef struct sieve_server_params {
+    uint64_t out_budget_bytes; /* device output arena; default 1 GiB */
+    uint32_t max_active;       /* requests on the device at once; default 1024 */
+    uint32_t step_tiles;       /* tiles per scheduler step; default 8 per CU */
+    uint32_t quantum_tiles;    /* tiles per request per step; default step_tiles / 8 */
+    uint32_t elem_bytes;       /* list element size, 4 or 8; default 8 */
+    uint32_t max_queue;        /* submitted but not admitted; default 1 << 20 */
+    uint32_t reserved;
+} sieve_server_params;
+
+/* One finished request.  Times are nanoseconds on the server's steady clock
+ * (0 = server creation): arrival (submit time or the scheduled arrival),
+ * admission (first piece on the device) and completion. */
+typedef struct sieve_completion {
+    uint64_t tag;
+    uint64_t count;       /* primes in [lo, hi) */
+    uint64_t lo, hi;
+    uint64_t t_arrival_ns, t_admit_ns, t_done_ns;
+    int32_t status;       /* SIEVE_OK, SIEVE_E_CANCELLED, SIEVE_E_NOMEM, ... */
+    int32_t mode;         /* 0 count, 1 list */
+} sieve_completion;
+
+typedef struct sieve_server_stats {
+    uint64_t steps;           /* scheduler steps run */
+    uint64_t tiles;           /* tiles sieved */
+    uint64_t ints;            /* integers sieved */
+    uint64_t completed;       /* requests completed (any status) */
+    uint64_t busy_ns;         /* time with a step on the device */
+    uint64_t elapsed_ns;      /* time since creation */
+    uint64_t arena_peak_bytes;
+    uint64_t queued, active;  /* at the time of the call */
+} sieve_server_stats;
+
+/* Creates a server on ctx (p == NULL: defaults).  *srv is set on success. */
+int sieve_server_create(sieve_ctx *ctx, const sieve_server_params *p, sieve_server **srv);
+
+/* Queues a request for [lo, hi); mode 0 counts, 1 lists.  `tag` identifies it
+ * in completions (tags must be unique among live requests).  Never blocks;
+ * SIEVE_E_BUSY when the queue is full, SIEVE_E_INVAL on a bad range. */
+int sieve_submit(sieve_server *srv, uint64_t lo, uint64_t hi, int mode, uint64_t tag);
+
+/* As sieve_submit, but the request becomes visible to the scheduler only at
+ * t_arrival_ns on the server clock (an open-loop load generator). */
+int sieve_submit_at(sieve_server *srv, uint64_t lo, uint64_t hi, int mode, uint64_t tag,
+                    uint64_t t_arrival_ns);
+
+/* Moves up to max finished requests into buf; waits up to wait_ms for at
+ * least one (0: no wait).  *n_out receives the number moved. */
+int sieve_poll(sieve_server *srv, sieve_completion *buf, int max, int wait_ms, int *n_out);
+
+/* Cancels a queued or active request: it completes with SIEVE_E_CANCELLED.
+ * SIEVE_E_INVAL if no live request has that tag. */
+int sieve_cancel(sieve_server *srv, uint64_t tag);
+
+/* Copies a completed list request's primes to dst (device or host memory,
+ * at most cap elements of the server's elem_bytes) and frees its arena space.
+ * *n_out receives the count.  SIEVE_E_CAPACITY (nothing copied, space kept)
+ * if cap is too small; SIEVE_E_INVAL for an unknown tag. */
+int sieve_server_fetch(sieve_server *srv, uint64_t tag, void *dst, uint64_t cap, uint64_t *n_out);
+
+/* Frees a completed list request's arena space without copying. */
+int sieve_server_release(sieve_server *srv, uint64_t tag);
+
+int sieve_server_get_stats(sieve_server *srv, sieve_server_stats *st);
+
+/* Current time on the server clock (ns since creation). */
+uint64_t sieve_server_now_ns(const sieve_server *srv);
+
+/* Stops the scheduler (pending requests are dropped) and frees the server;
+ * the context can be used again afterwards. */
+int sieve_server_destroy(sieve_server *srv);
+
 /* Text for a status code (static storage). */
 const char *sieve_strerror(int status);
 

@@ -19,7 +19,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Sieve", "SieveError", "Params", "list_bound", "wheel_start", "plan_range", "probe_lds",
+__all__ = ["Sieve", "Server", "SieveError", "Params", "list_bound", "wheel_start", "plan_range", "probe_lds",
            "lib_path", "load_library", "SIEVE_OK", "SIEVE_E_CAPACITY"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -51,6 +51,32 @@ class Params(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class ServerParams(ctypes.Structure):
+    """sieve_server_params (include/sieve.h); zero fields select the defaults."""
+    _fields_ = [("out_budget_bytes", ctypes.c_uint64), ("max_active", ctypes.c_uint32),
+                ("step_tiles", ctypes.c_uint32), ("quantum_tiles", ctypes.c_uint32),
+                ("elem_bytes", ctypes.c_uint32), ("max_queue", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("count", ctypes.c_uint64), ("lo", ctypes.c_uint64),
+                ("hi", ctypes.c_uint64), ("t_arrival_ns", ctypes.c_uint64),
+                ("t_admit_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64),
+                ("status", ctypes.c_int32), ("mode", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in ("steps", "tiles", "ints", "completed", "busy_ns",
+                                               "elapsed_ns", "arena_peak_bytes", "queued", "active")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class SieveError(RuntimeError):
@@ -97,6 +123,17 @@ def load_library():
                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
         "sieve_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "sieve_last_error": (ctypes.c_int, [_p]),
+        "sieve_server_create": (ctypes.c_int, [_p, ctypes.POINTER(ServerParams), ctypes.POINTER(_p)]),
+        "sieve_submit": (ctypes.c_int, [_p, _u64, _u64, ctypes.c_int, _u64]),
+        "sieve_submit_at": (ctypes.c_int, [_p, _u64, _u64, ctypes.c_int, _u64, _u64]),
+        "sieve_poll": (ctypes.c_int, [_p, ctypes.POINTER(Completion), ctypes.c_int, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int)]),
+        "sieve_cancel": (ctypes.c_int, [_p, _u64]),
+        "sieve_server_fetch": (ctypes.c_int, [_p, _u64, _p, _u64, ctypes.POINTER(_u64)]),
+        "sieve_server_release": (ctypes.c_int, [_p, _u64]),
+        "sieve_server_get_stats": (ctypes.c_int, [_p, ctypes.POINTER(ServerStats)]),
+        "sieve_server_now_ns": (_u64, [_p]),
+        "sieve_server_destroy": (ctypes.c_int, [_p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -301,3 +338,76 @@ class Sieve:
         _check(self._lib.sieve_get_timing(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)),
                "sieve_get_timing")
         return a.value, b.value, n.value
+
+
+class Server:
+    """Continuous-batching range-query server on a Sieve context.
+
+    While the server exists the context must not be used for other calls.
+    """
+
+    def __init__(self, sieve: "Sieve", **params):
+        self._sieve = sieve
+        self._lib = sieve._lib
+        p = ServerParams()
+        for k, v in params.items():
+            setattr(p, k, v)
+        h = _p()
+        _check(self._lib.sieve_server_create(sieve._h, ctypes.byref(p), ctypes.byref(h)),
+               "sieve_server_create")
+        self._h = h
+        self.elem_bytes = params.get("elem_bytes", 8) or 8
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.sieve_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def now_ns(self) -> int:
+        return int(self._lib.sieve_server_now_ns(self._h))
+
+    def submit(self, lo: int, hi: int, mode: int, tag: int, at_ns: int | None = None) -> None:
+        if at_ns is None:
+            code = self._lib.sieve_submit(self._h, lo, hi, mode, tag)
+        else:
+            code = self._lib.sieve_submit_at(self._h, lo, hi, mode, tag, at_ns)
+        _check(code, "sieve_submit")
+
+    def poll(self, max_items: int = 4096, wait_ms: int = 0) -> list[dict]:
+        buf = (Completion * max_items)()
+        n = ctypes.c_int()
+        _check(self._lib.sieve_poll(self._h, buf, max_items, wait_ms, ctypes.byref(n)), "sieve_poll")
+        return [buf[i].as_dict() for i in range(n.value)]
+
+    def cancel(self, tag: int) -> int:
+        return int(self._lib.sieve_cancel(self._h, tag))
+
+    def fetch(self, tag: int, count: int, device: bool = True):
+        """Copies a finished list result into a new tensor and frees its space."""
+        torch = _torch()
+        dev = "cuda:%d" % self._sieve.device if device else "cpu"
+        out = torch.empty(max(count, 1), dtype=_dtype_for(self.elem_bytes), device=dev)
+        n = _u64()
+        _check(self._lib.sieve_server_fetch(self._h, tag, out.data_ptr(), out.numel(), ctypes.byref(n)),
+               "sieve_server_fetch")
+        return out[: n.value]
+
+    def release(self, tag: int) -> None:
+        _check(self._lib.sieve_server_release(self._h, tag), "sieve_server_release")
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(self._lib.sieve_server_get_stats(self._h, ctypes.byref(st)), "sieve_server_get_stats")
+        return st.as_dict()

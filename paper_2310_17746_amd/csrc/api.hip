@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../../include/sieve.h"
+#include "runtime.h"
 #include "sieve_internal.h"
 #include "wheel.h"
 
@@ -28,6 +29,7 @@ hipError_t launch_compact(const CompactArgs &a, uint32_t grid, hipStream_t s);
 }  // namespace sieve
 
 using namespace sieve;
+using sieve::rt::DevBuf;
 
 namespace {
 
@@ -67,94 +69,7 @@ std::vector<uint32_t> host_small_primes(uint64_t limit)
     return out;
 }
 
-template <typename T>
-struct DevBuf {
-    T *p = nullptr;
-    size_t n = 0;
-    // Grows to at least `need` elements (contents are not kept).
-    bool reserve(size_t need, uint64_t *gen = nullptr)
-    {
-        if (need <= n && p)
-            return true;
-        size_t m = std::max<size_t>(need, 1);
-        if (p)
-            m = std::max(m, n + n / 2);
-        if (p)
-            (void)hipFree(p);
-        p = nullptr;
-        n = 0;
-        if (gen)
-            ++*gen;
-        T *q = nullptr;
-        if (hipMalloc((void **)&q, m * sizeof(T)) != hipSuccess) {
-            (void)hipGetLastError();
-            return false;
-        }
-        p = q;
-        n = m;
-        return true;
-    }
-    void release()
-    {
-        if (p)
-            (void)hipFree(p);
-        p = nullptr;
-        n = 0;
-    }
-};
-
 }  // namespace
-
-struct sieve_ctx {
-    int device = 0;
-    int cus = 0;
-    uint32_t lds_max = 0;
-    sieve_params prm{};
-    hipStream_t stream = nullptr;
-    int last_error = SIEVE_OK;
-
-    // Resident base primes (>= 5) and derived constants.
-    uint64_t limit = 0;
-    std::vector<uint32_t> h_primes;
-    DevBuf<PrimeConst> d_prm;
-    DevBuf<uint32_t> d_pidx;
-    DevBuf<uint2> d_items;
-    DevBuf<uint32_t> d_item_prefix;
-    uint32_t first_mark = 0, k_split = 0;
-
-    // Presieve tables.
-    DevBuf<uint2> d_pstab;
-    PsGroup groups[kMaxGroups]{};
-    uint32_t ngroups = 0;
-    uint32_t restore1 = 0, restore5 = 0;
-
-    // Job scratch.
-    DevBuf<unsigned char> d_blob;  // JobHeader | RangeDesc[] | list_idx[] | list_chunk0[]
-    DevBuf<unsigned long long> d_counters;
-    DevBuf<unsigned long long> d_counts;
-    DevBuf<int32_t> d_status;
-    DevBuf<unsigned long long> d_bitmap;
-    DevBuf<uint32_t> d_chunk_counts;
-    DevBuf<unsigned long long> d_chunk_off;
-    unsigned char *h_blob = nullptr;  // pinned staging for the blob
-    size_t h_blob_n = 0;
-    unsigned long long *h_counts = nullptr;  // pinned
-    int32_t *h_status = nullptr;             // pinned
-    unsigned long long *h_flag = nullptr;    // pinned copy of the kernels' error flag
-    uint64_t cap_ranges = 0, cap_list = 0, cap_chunks = 0;
-
-    // Graph of the job kernels; valid while gen == graph_gen.
-    hipGraphExec_t graph = nullptr;
-    hipGraph_t graph_src = nullptr;
-    uint64_t graph_gen = ~0ull;
-    uint64_t gen = 0;
-
-    // Optional event timing of the sieve kernel and the post-processing.
-    int timing = 0;
-    hipEvent_t ev[3]{};
-    double t_sieve_ms = 0, t_post_ms = 0;
-    uint64_t t_jobs = 0;
-};
 
 namespace {
 
@@ -723,6 +638,25 @@ void destroy_ctx(sieve_ctx *c)
 }
 
 }  // namespace
+
+namespace sieve {
+namespace rt {
+int set_err(sieve_ctx *c, int e) { return ::set_err(c, e); }
+int hip_status(hipError_t e) { return ::hip_status(e); }
+uint64_t isqrt_host(uint64_t n) { return ::isqrt_host(n); }
+void plan_range(uint64_t lo, uint64_t hi, uint32_t pw, uint64_t &ntiles, uint64_t &base, uint32_t &last_words)
+{
+    ::plan_range(lo, hi, pw, ntiles, base, last_words);
+}
+int run_job(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, const uint8_t *mode,
+            const uint64_t *off, const uint64_t *cap, int elem_bytes, void *out, uint64_t *counts, int32_t *status,
+            hipStream_t stream, bool use_graph)
+{
+    return ::run_job(c, n, lo, hi, mode, off, cap, elem_bytes, out, counts, status, stream, use_graph);
+}
+int grow_base_primes(sieve_ctx *c, uint64_t limit) { return ::grow_base_primes(c, limit); }
+}  // namespace rt
+}  // namespace sieve
 
 extern "C" {
 

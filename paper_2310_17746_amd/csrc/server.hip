@@ -1,0 +1,517 @@
+// Serving engine: continuous batching of range queries over one context.
+//
+// A scheduler thread owns the context.  Requests arrive (immediately, or at
+// a scheduled time on the server clock), wait in FIFO order, and are admitted
+// while slots are free and, for list requests, while their bounded output
+// fits the device output arena.  Each step cuts every active request into a
+// tile-aligned piece (up to quantum_tiles tiles, round-robin, step_tiles in
+// all) and runs the pieces as one batched job.  Tile-aligned pieces of
+// [lo, hi) are themselves ranges whose tiles coincide with the request's own
+// tiles, so counts add up and list pieces concatenate in order: a request's
+// result equals the stand-alone result for its range.
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/sieve.h"
+#include "runtime.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+// First-fit allocator of byte offsets in the output arena (256-byte grains),
+// with coalescing of freed neighbours.
+class Arena {
+public:
+    void init(uint64_t size)
+    {
+        size_ = size;
+        free_.clear();
+        if (size)
+            free_[0] = size;
+        used_ = peak_ = 0;
+    }
+    bool alloc(uint64_t n, uint64_t &off)
+    {
+        n = (n + 255) / 256 * 256;
+        if (n == 0)
+            n = 256;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                off = it->first;
+                const uint64_t rest = it->second - n;
+                free_.erase(it);
+                if (rest)
+                    free_[off + n] = rest;
+                used_ += n;
+                peak_ = std::max(peak_, used_);
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(uint64_t off, uint64_t n)
+    {
+        n = (n + 255) / 256 * 256;
+        if (n == 0)
+            n = 256;
+        used_ -= n;
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    uint64_t peak() const { return peak_; }
+
+private:
+    uint64_t size_ = 0, used_ = 0, peak_ = 0;
+    std::map<uint64_t, uint64_t> free_;
+};
+
+struct Request {
+    uint64_t tag = 0, lo = 0, hi = 0;
+    int mode = 0;
+    uint64_t t_arr = 0, t_admit = 0;
+    uint64_t ntiles = 0, base = 0;
+    uint32_t last_words = 0;
+    uint64_t next_tile = 0;
+    uint64_t count = 0;
+    uint64_t off_bytes = 0, cap_elems = 0, arena_bytes = 0;
+    bool has_arena = false;
+    bool cancelled = false;
+};
+
+struct Finished {
+    uint64_t off_bytes, arena_bytes, count;
+};
+
+}  // namespace
+
+struct sieve_server {
+    sieve_ctx *ctx = nullptr;
+    sieve_server_params p{};
+    unsigned char *arena_base = nullptr;
+    Arena arena;
+    Clock::time_point t0;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::multimap<uint64_t, Request *> inbox;  // by arrival time
+    std::deque<Request *> pending;             // arrived, FIFO
+    std::vector<Request *> active;
+    std::deque<sieve_completion> done;
+    std::unordered_map<uint64_t, Request *> live;  // queued or active, by tag
+    std::unordered_map<uint64_t, Finished> results;
+    size_t rr = 0;
+    bool stop = false;
+    std::thread th;
+
+    sieve_server_stats st{};
+
+    uint64_t now() const
+    {
+        return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now() - t0).count();
+    }
+};
+
+namespace {
+
+void complete_locked(sieve_server *s, Request *r, int status, uint64_t t)
+{
+    sieve_completion c;
+    memset(&c, 0, sizeof c);
+    c.tag = r->tag;
+    c.count = r->count;
+    c.lo = r->lo;
+    c.hi = r->hi;
+    c.t_arrival_ns = r->t_arr;
+    c.t_admit_ns = r->t_admit;
+    c.t_done_ns = t;
+    c.status = status;
+    c.mode = r->mode;
+    s->done.push_back(c);
+    s->live.erase(r->tag);
+    if (r->has_arena) {
+        if (status == SIEVE_OK && r->mode)
+            s->results[r->tag] = Finished{r->off_bytes, r->arena_bytes, r->count};
+        else
+            s->arena.release(r->off_bytes, r->arena_bytes);
+    }
+    s->st.completed++;
+    delete r;
+}
+
+void scheduler(sieve_server *s)
+{
+    sieve_ctx *c = s->ctx;
+    (void)hipSetDevice(c->device);
+    const uint32_t pw = c->prm.segment_bytes / 8;
+    const uint64_t S = 192ull * pw;  // integers per tile
+    const uint32_t eb = s->p.elem_bytes;
+    std::vector<uint64_t> lo, hi, off, cap, counts;
+    std::vector<uint8_t> mode;
+    std::vector<int32_t> status;
+    std::vector<std::pair<Request *, uint64_t>> pieces;  // request, tiles taken
+
+    for (;;) {
+        uint64_t need_limit = 0;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            for (;;) {
+                if (s->stop)
+                    return;
+                const uint64_t t = s->now();
+                while (!s->inbox.empty() && s->inbox.begin()->first <= t) {
+                    s->pending.push_back(s->inbox.begin()->second);
+                    s->inbox.erase(s->inbox.begin());
+                }
+                // Admission: FIFO, by free slots and output arena.
+                while (!s->pending.empty() && s->active.size() < s->p.max_active) {
+                    Request *r = s->pending.front();
+                    if (r->cancelled) {
+                        s->pending.pop_front();
+                        complete_locked(s, r, SIEVE_E_CANCELLED, t);
+                        continue;
+                    }
+                    if (r->mode) {
+                        r->cap_elems = sieve_list_bound(r->lo, r->hi);
+                        r->arena_bytes = std::max<uint64_t>(r->cap_elems * eb, 1);
+                        if (r->arena_bytes > s->p.out_budget_bytes) {
+                            s->pending.pop_front();
+                            complete_locked(s, r, SIEVE_E_NOMEM, t);
+                            continue;
+                        }
+                        if (!s->arena.alloc(r->arena_bytes, r->off_bytes))
+                            break;  // head of line waits for memory
+                        r->has_arena = true;
+                    }
+                    r->t_admit = t;
+                    s->pending.pop_front();
+                    s->active.push_back(r);
+                    if (r->hi > 4)
+                        need_limit = std::max(need_limit, sieve::rt::isqrt_host(r->hi - 1));
+                }
+                // Drop cancelled active requests.
+                for (size_t i = 0; i < s->active.size();) {
+                    if (s->active[i]->cancelled) {
+                        complete_locked(s, s->active[i], SIEVE_E_CANCELLED, t);
+                        s->active.erase(s->active.begin() + i);
+                    } else {
+                        ++i;
+                    }
+                }
+                if (!s->active.empty())
+                    break;
+                s->cv_done.notify_all();
+                if (!s->inbox.empty()) {
+                    const uint64_t wake = s->inbox.begin()->first;
+                    s->cv_work.wait_for(lk, std::chrono::nanoseconds(wake > t ? wake - t : 0));
+                } else {
+                    s->cv_work.wait(lk);
+                }
+            }
+            // Build one step: round-robin pieces of the active requests.
+            lo.clear();
+            hi.clear();
+            off.clear();
+            cap.clear();
+            mode.clear();
+            pieces.clear();
+            uint64_t budget = s->p.step_tiles;
+            const size_t n = s->active.size();
+            for (size_t k = 0; k < n && budget; ++k) {
+                Request *r = s->active[(s->rr + k) % n];
+                const uint64_t left = r->ntiles - r->next_tile;
+                uint64_t take = std::min<uint64_t>(std::min<uint64_t>(left, s->p.quantum_tiles), budget);
+                if (r->ntiles == 0)
+                    take = 0;  // no wheel values: one tile-less piece counts 2 and 3
+                else if (take == 0)
+                    continue;
+                const uint64_t k0 = r->next_tile, k1 = k0 + take;
+                lo.push_back(k0 == 0 ? r->lo : r->base + k0 * S);
+                hi.push_back(r->ntiles == 0 || k1 == r->ntiles ? r->hi : r->base + k1 * S);
+                mode.push_back((uint8_t)r->mode);
+                off.push_back(r->mode ? r->off_bytes / eb + r->count : 0);
+                cap.push_back(r->mode ? r->cap_elems - r->count : 0);
+                pieces.emplace_back(r, take);
+                budget -= take;
+            }
+            s->rr = n ? (s->rr + 1) % n : 0;
+        }
+        int rc = SIEVE_OK;
+        if (need_limit > c->limit)
+            rc = sieve::rt::grow_base_primes(c, need_limit);
+        const uint64_t m = lo.size();
+        counts.assign(m, 0);
+        status.assign(m, 0);
+        const uint64_t tb = s->now();
+        if (rc == SIEVE_OK && m)
+            rc = sieve::rt::run_job(c, m, lo.data(), hi.data(), mode.data(), off.data(), cap.data(), (int)eb,
+                                    s->arena_base, counts.data(), status.data(), nullptr, c->prm.use_graph != 0);
+        const uint64_t te = s->now();
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->st.steps++;
+            s->st.busy_ns += te - tb;
+            for (uint64_t i = 0; i < m; ++i) {
+                Request *r = pieces[i].first;
+                s->st.tiles += pieces[i].second;
+                s->st.ints += hi[i] - lo[i];
+                int stt = rc != SIEVE_OK ? rc : status[i];
+                r->count += counts[i];
+                r->next_tile += pieces[i].second;
+                if (stt != SIEVE_OK || r->next_tile >= r->ntiles) {
+                    s->active.erase(std::find(s->active.begin(), s->active.end(), r));
+                    complete_locked(s, r, stt, te);
+                }
+            }
+            s->cv_done.notify_all();
+        }
+    }
+}
+
+int submit(sieve_server *s, uint64_t lo, uint64_t hi, int mode, uint64_t tag, bool at, uint64_t t_arr)
+{
+    if (!s || lo > hi || hi > SIEVE_MAX_HI || (mode != 0 && mode != 1))
+        return SIEVE_E_INVAL;
+    if (mode && s->p.elem_bytes == 4 && hi > lo && hi - 1 > 0xFFFFFFFFull)
+        return SIEVE_E_DTYPE;
+    if (hi > 4 && sieve::rt::isqrt_host(hi - 1) >= (1ull << 32))
+        return SIEVE_E_RANGE;
+    Request *r = new (std::nothrow) Request();
+    if (!r)
+        return SIEVE_E_NOMEM;
+    r->tag = tag;
+    r->lo = lo;
+    r->hi = hi;
+    r->mode = mode;
+    sieve::rt::plan_range(lo, hi, s->ctx->prm.segment_bytes / 8, r->ntiles, r->base, r->last_words);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->live.count(tag) || s->results.count(tag)) {
+            delete r;
+            return SIEVE_E_INVAL;
+        }
+        if (s->inbox.size() + s->pending.size() >= s->p.max_queue) {
+            delete r;
+            return SIEVE_E_BUSY;
+        }
+        r->t_arr = at ? t_arr : s->now();
+        s->live[tag] = r;
+        s->inbox.emplace(r->t_arr, r);
+    }
+    s->cv_work.notify_one();
+    return SIEVE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sieve_server_create(sieve_ctx *ctx, const sieve_server_params *p, sieve_server **out)
+{
+    if (!ctx || !out)
+        return SIEVE_E_INVAL;
+    *out = nullptr;
+    sieve_server_params q;
+    memset(&q, 0, sizeof q);
+    if (p)
+        q = *p;
+    if (!q.out_budget_bytes)
+        q.out_budget_bytes = 1ull << 30;
+    if (!q.max_active)
+        q.max_active = 1024;
+    if (!q.step_tiles)
+        q.step_tiles = 8u * (uint32_t)ctx->cus;
+    if (!q.quantum_tiles)
+        q.quantum_tiles = std::max<uint32_t>(1, q.step_tiles / 8);
+    if (!q.elem_bytes)
+        q.elem_bytes = 8;
+    if (!q.max_queue)
+        q.max_queue = 1u << 20;
+    if (q.elem_bytes != 4 && q.elem_bytes != 8)
+        return SIEVE_E_DTYPE;
+    sieve_server *s = new (std::nothrow) sieve_server();
+    if (!s)
+        return SIEVE_E_NOMEM;
+    s->ctx = ctx;
+    s->p = q;
+    if (hipSetDevice(ctx->device) != hipSuccess ||
+        hipMalloc((void **)&s->arena_base, q.out_budget_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        delete s;
+        return SIEVE_E_NOMEM;
+    }
+    s->arena.init(q.out_budget_bytes);
+    s->t0 = Clock::now();
+    try {
+        s->th = std::thread(scheduler, s);
+    } catch (...) {
+        (void)hipFree(s->arena_base);
+        delete s;
+        return SIEVE_E_NOMEM;
+    }
+    *out = s;
+    return SIEVE_OK;
+}
+
+int sieve_submit(sieve_server *srv, uint64_t lo, uint64_t hi, int mode, uint64_t tag)
+{
+    return submit(srv, lo, hi, mode, tag, false, 0);
+}
+
+int sieve_submit_at(sieve_server *srv, uint64_t lo, uint64_t hi, int mode, uint64_t tag, uint64_t t_arrival_ns)
+{
+    return submit(srv, lo, hi, mode, tag, true, t_arrival_ns);
+}
+
+int sieve_poll(sieve_server *srv, sieve_completion *buf, int max, int wait_ms, int *n_out)
+{
+    if (!srv || !n_out || max < 0 || (max && !buf))
+        return SIEVE_E_INVAL;
+    std::unique_lock<std::mutex> lk(srv->mu);
+    if (srv->done.empty() && wait_ms > 0)
+        srv->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms), [&] { return !srv->done.empty(); });
+    int n = 0;
+    while (n < max && !srv->done.empty()) {
+        buf[n++] = srv->done.front();
+        srv->done.pop_front();
+    }
+    *n_out = n;
+    return SIEVE_OK;
+}
+
+int sieve_cancel(sieve_server *srv, uint64_t tag)
+{
+    if (!srv)
+        return SIEVE_E_INVAL;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        auto it = srv->live.find(tag);
+        if (it == srv->live.end())
+            return SIEVE_E_INVAL;
+        Request *r = it->second;
+        r->cancelled = true;
+        // Not yet arrived: complete it here.
+        for (auto jt = srv->inbox.begin(); jt != srv->inbox.end(); ++jt) {
+            if (jt->second == r) {
+                srv->inbox.erase(jt);
+                complete_locked(srv, r, SIEVE_E_CANCELLED, srv->now());
+                srv->cv_done.notify_all();
+                return SIEVE_OK;
+            }
+        }
+    }
+    srv->cv_work.notify_one();
+    return SIEVE_OK;
+}
+
+int sieve_server_fetch(sieve_server *srv, uint64_t tag, void *dst, uint64_t cap, uint64_t *n_out)
+{
+    if (!srv || !n_out)
+        return SIEVE_E_INVAL;
+    Finished f;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        auto it = srv->results.find(tag);
+        if (it == srv->results.end())
+            return SIEVE_E_INVAL;
+        f = it->second;
+        *n_out = f.count;
+        if (f.count > cap)
+            return SIEVE_E_CAPACITY;
+        if (f.count && !dst)
+            return SIEVE_E_INVAL;
+    }
+    if (f.count) {
+        (void)hipSetDevice(srv->ctx->device);
+        if (hipMemcpy(dst, srv->arena_base + f.off_bytes, f.count * srv->p.elem_bytes, hipMemcpyDefault) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            return SIEVE_E_DEVICE;
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->results.erase(tag);
+        srv->arena.release(f.off_bytes, f.arena_bytes);
+    }
+    srv->cv_work.notify_one();  // memory freed: admission may proceed
+    return SIEVE_OK;
+}
+
+int sieve_server_release(sieve_server *srv, uint64_t tag)
+{
+    if (!srv)
+        return SIEVE_E_INVAL;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->results.find(tag);
+    if (it == srv->results.end())
+        return SIEVE_E_INVAL;
+    srv->arena.release(it->second.off_bytes, it->second.arena_bytes);
+    srv->results.erase(it);
+    srv->cv_work.notify_one();  // memory freed: admission may proceed
+    return SIEVE_OK;
+}
+
+int sieve_server_get_stats(sieve_server *srv, sieve_server_stats *st)
+{
+    if (!srv || !st)
+        return SIEVE_E_INVAL;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    *st = srv->st;
+    st->elapsed_ns = srv->now();
+    st->arena_peak_bytes = srv->arena.peak();
+    st->queued = srv->inbox.size() + srv->pending.size();
+    st->active = srv->active.size();
+    return SIEVE_OK;
+}
+
+uint64_t sieve_server_now_ns(const sieve_server *srv) { return srv ? srv->now() : 0; }
+
+int sieve_server_destroy(sieve_server *srv)
+{
+    if (!srv)
+        return SIEVE_OK;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+    }
+    srv->cv_work.notify_all();
+    if (srv->th.joinable())
+        srv->th.join();
+    for (auto &kv : srv->inbox)
+        delete kv.second;
+    for (Request *r : srv->pending)
+        delete r;
+    for (Request *r : srv->active)
+        delete r;
+    if (srv->arena_base) {
+        (void)hipSetDevice(srv->ctx->device);
+        (void)hipFree(srv->arena_base);
+    }
+    delete srv;
+    return SIEVE_OK;
+}
+
+}  // extern "C"

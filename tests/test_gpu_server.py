@@ -1,0 +1,120 @@
+"""Serving engine on the GPU: every request's result in the mix equals its
+result alone (bit-exact) and the oracle's; admission by output memory,
+cancellation and scheduled arrivals behave as documented."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from conftest import read_golden
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+pkg = pytest.importorskip("paper_2310_17746_amd")
+
+
+def _u(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+@pytest.fixture(scope="module")
+def sv():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    s = pkg.Sieve(0)
+    s.base_primes(10 ** 6)
+    yield s
+    s.close()
+
+
+def _drain(srv, n, timeout_s=120):
+    got = {}
+    t_end = time.time() + timeout_s
+    while len(got) < n and time.time() < t_end:
+        for c in srv.poll(4096, wait_ms=50):
+            got[c["tag"]] = c
+    assert len(got) == n, "server did not finish: %d of %d" % (len(got), n)
+    return got
+
+
+def test_alone_vs_mix_with_long_job(sv):
+    pi = {int(x): int(v) for x, v in read_golden("pi_values.txt")}
+    rng = np.random.default_rng(5)
+    n = 120
+    lo = np.floor(10 ** rng.uniform(0, 11.5, n)).astype(np.uint64)
+    hi = lo + np.floor(10 ** rng.uniform(0, 7, n)).astype(np.uint64)
+    mode = (rng.random(n) < 0.4).astype(int)
+    lo[:4] = [0, 2, 3, 10 ** 6]
+    hi[:4] = [0, 4, 3, 10 ** 6 + 1]
+    alone_c = [sv.count(int(a), int(b)) for a, b in zip(lo, hi)]
+    alone_l = {i: _u(sv.list(int(lo[i]), int(hi[i]), elem_bytes=8)) for i in range(n) if mode[i]}
+    long_tag = 10 ** 6
+    with pkg.Server(sv, out_budget_bytes=512 << 20, step_tiles=96, quantum_tiles=4) as srv:
+        srv.submit(2, 10 ** 10 + 1, 0, long_tag)
+        for i in range(n):
+            srv.submit(int(lo[i]), int(hi[i]), int(mode[i]), i)
+        got = _drain(srv, n + 1)
+        assert got[long_tag]["status"] == 0 and got[long_tag]["count"] == pi[10 ** 10]
+        for i in range(n):
+            c = got[i]
+            assert c["status"] == 0, (i, c)
+            assert c["count"] == alone_c[i], (i, int(lo[i]), int(hi[i]))
+            if mode[i]:
+                lst = _u(srv.fetch(i, c["count"]))
+                assert np.array_equal(lst, alone_l[i]), i
+                assert np.array_equal(lst, oracle.primes(int(lo[i]), int(hi[i]), elem_bytes=8)), i
+        # the long job shares the device: most short requests finish first
+        short_done = np.array([got[i]["t_done_ns"] for i in range(n)])
+        assert np.mean(short_done < got[long_tag]["t_done_ns"]) > 0.9
+        st = srv.stats()
+        assert st["completed"] == n + 1 and st["active"] == 0
+
+
+def test_cancel_long_job(sv):
+    with pkg.Server(sv, step_tiles=32, quantum_tiles=2) as srv:
+        srv.submit(2, 10 ** 11 + 1, 0, 7)
+        time.sleep(0.05)
+        assert srv.cancel(7) == 0
+        (c,) = _drain(srv, 1).values()
+        assert c["status"] == pkg.SIEVE_E_CANCELLED
+        assert srv.cancel(7) == pkg.SIEVE_E_INVAL  # no longer live
+
+
+def test_admission_by_output_budget(sv):
+    lo, hi = 10 ** 9, 10 ** 9 + 2 * 10 ** 6
+    bound = pkg.list_bound(lo, hi) * 8
+    budget = (bound * 3) // 2                 # one list request fits, not two
+    with pkg.Server(sv, out_budget_bytes=budget) as srv:
+        srv.submit(0, 10 ** 8, 1, 99)         # bound exceeds the whole budget
+        srv.submit(lo, hi, 1, 1)
+        srv.submit(lo, hi, 1, 2)
+        first = {}
+        t_end = time.time() + 60
+        while len(first) < 2 and time.time() < t_end:
+            for c in srv.poll(16, wait_ms=50):
+                first[c["tag"]] = c
+        assert first[99]["status"] == pkg.SIEVE_E_NOMEM
+        assert first[1]["status"] == 0
+        time.sleep(0.2)
+        assert 2 not in first and srv.stats()["queued"] == 1  # waits for memory
+        want = oracle.primes(lo, hi, elem_bytes=8)
+        assert np.array_equal(_u(srv.fetch(1, first[1]["count"])), want)  # frees its space
+        (c2,) = _drain(srv, 1).values()
+        assert c2["tag"] == 2 and c2["status"] == 0 and c2["t_admit_ns"] > first[1]["t_done_ns"]
+        assert np.array_equal(_u(srv.fetch(2, c2["count"])), want)
+
+
+def test_scheduled_arrivals(sv):
+    with pkg.Server(sv) as srv:
+        t0 = srv.now_ns()
+        arr = [t0 + k * 20_000_000 for k in range(5)]  # every 20 ms
+        for k, t in enumerate(arr):
+            srv.submit(10 ** 10, 10 ** 10 + 10 ** 6, 0, k, at_ns=t)
+        got = _drain(srv, 5)
+        want = oracle.count(10 ** 10, 10 ** 10 + 10 ** 6)
+        for k in range(5):
+            c = got[k]
+            assert c["count"] == want
+            assert c["t_arrival_ns"] == arr[k] and c["t_admit_ns"] >= arr[k] and c["t_done_ns"] >= c["t_admit_ns"]
