@@ -16,6 +16,18 @@ m coprime to 6 with max(p^2, tile base) <= m*p < tile-span end.
 
 The CPU baseline is the oracle (plain byte-per-integer segmented sieve, all
 host threads) timed on a bounded slice of the same workload.
+
+"extras" reports the other measured configurations in the same line:
+* list_1e9: the sorted uint32 list of the primes in [2, 10^9]; the
+  compaction phase (finalize + compaction kernels, HIP events) against HBM
+  peak, with algorithmic bytes = 4 B per prime written + 8 B per bitmap word
+  read.
+* batch_4096: the 4096 seeded uneven ranges (half listed as uint64) in one
+  batched call replaying a captured graph, against the same ranges as one
+  plain call each; primes/s counts every prime counted or listed.
+* serve_2000: 2000 seeded requests with Poisson arrivals at 0.8 x the
+  saturated request rate (measured first with all requests at t = 0) and the
+  count of [2, 10^12] submitted at t = 0; p50/p99 of completion - arrival.
 """
 from __future__ import annotations
 
@@ -73,6 +85,125 @@ def lds_work(lo: int, hi: int, segment_bytes: int) -> tuple[int, int]:
     return marks, int(words)
 
 
+def bench_list(pkg, torch, params, steps=5):
+    """Config 2: sorted uint32 list of the primes in [2, 10^9]."""
+    lo, hi = 2, 10 ** 9 + 1
+    s = pkg.Sieve(0, params)
+    s.ensure_base_for(hi)
+    out = torch.empty(pkg.list_bound(lo, hi), dtype=torch.int32, device="cuda")
+    n = s.list(lo, hi, out=out, elem_bytes=4).numel()
+    torch.cuda.synchronize()
+    s.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.list(lo, hi, out=out, elem_bytes=4)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    sieve_ms, post_ms, jobs = s.timing()
+    s.close()
+    words = ((hi - lo + 5) // 6 + 31) // 32
+    post = post_ms / jobs
+    nbytes = 4 * n + 8 * words
+    gbs = nbytes / (post * 1e-3) / 1e9
+    return {"workload": "sorted uint32 list of the primes in [2, 10^9]", "primes": n,
+            "ms_per_call": round(dt * 1e3, 3), "ints_per_s": round((hi - lo) / dt, 1),
+            "primes_per_s": round(n / dt, 1), "sieve_kernel_ms": round(sieve_ms / jobs, 4),
+            "compaction_ms": round(post, 4),
+            "compaction_roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0,
+                                    "unit": "GB/s", "frac": round(gbs / 8000.0, 4),
+                                    "algorithmic_bytes": nbytes}}
+
+
+def bench_batch(pkg, torch, params, workloads, steps=3):
+    """Config 4: 4096 seeded uneven ranges, half listed as uint64."""
+    lo, hi, mode = workloads.batch_ranges(0)
+    s = pkg.Sieve(0, dict(params, use_graph=1))
+    s.ensure_base_for(int(hi.max()))
+    cap = np.array([pkg.list_bound(int(a), int(b)) if m else 0 for a, b, m in zip(lo, hi, mode)],
+                   dtype=np.uint64)
+    off = np.concatenate([[0], np.cumsum(cap)[:-1]]).astype(np.uint64)
+    out = torch.empty(int(cap.sum()) + 1, dtype=torch.int64, device="cuda")
+    counts, status = s.list_batch(lo, hi, mode, out, off, cap, elem_bytes=8)  # warm-up + capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        counts, status = s.list_batch(lo, hi, mode, out, off, cap, elem_bytes=8)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    # the same ranges as one plain call each
+    t1 = time.perf_counter()
+    for a, b, m, o, c in zip(lo.tolist(), hi.tolist(), mode.tolist(), off.tolist(), cap.tolist()):
+        if m:
+            s.list(a, b, out=out[o:o + max(c, 1)], elem_bytes=8)
+        else:
+            s.count(a, b)
+    torch.cuda.synchronize()
+    dt_single = time.perf_counter() - t1
+    s.close()
+    ints = int((hi - lo).sum())
+    primes = int(counts.sum())
+    return {"workload": "4096 ranges (seed 0): lo log-uniform [1e6, 1e15], length log-uniform "
+                        "[1e3, 1e8], half listed as uint64", "ok": bool(np.all(status == 0)),
+            "ints": ints, "primes": primes, "listed": int(counts[mode == 1].sum()),
+            "ms_per_batch": round(dt * 1e3, 3), "ints_per_s": round(ints / dt, 1),
+            "primes_per_s": round(primes / dt, 1),
+            "per_range_ms": round(dt_single * 1e3, 3),
+            "batched_vs_per_range": round(dt_single / dt, 3)}
+
+
+def bench_serve(pkg, workloads):
+    """Config 5: Poisson request stream with the [2, 10^12] count job beside it."""
+    lo, hi, mode, gaps = workloads.serving_requests(1)
+    long_lo, long_hi = workloads.LONG_JOB
+    s = pkg.Sieve(0)
+    s.ensure_base_for(max(int(hi.max()), long_hi))
+    n = len(lo)
+
+    def run(arrivals_ns):
+        with pkg.Server(s, out_budget_bytes=64 << 30, elem_bytes=8) as srv:
+            t0 = srv.now_ns() + 2_000_000
+            srv.submit(long_lo, long_hi, 0, n, at_ns=t0)
+            for i in range(n):
+                srv.submit(int(lo[i]), int(hi[i]), int(mode[i]), i, at_ns=t0 + int(arrivals_ns[i]))
+            done = {}
+            t_end = time.time() + 300
+            while len(done) < n + 1:
+                if time.time() > t_end:
+                    raise RuntimeError("serving run did not finish")
+                for c in srv.poll(4096, wait_ms=20):
+                    done[c["tag"]] = c
+                    if c["mode"] == 1 and c["status"] == 0:
+                        srv.release(c["tag"])
+            st = srv.stats()
+        return done, st, t0
+
+    # saturated rate: every request arrives at once
+    done, st, t0 = run(np.zeros(n))
+    t_sat = max(done[i]["t_done_ns"] for i in range(n)) - t0
+    mu = n / (t_sat * 1e-9)
+    lam = 0.8 * mu
+    arrivals = np.cumsum(gaps) / lam * 1e9
+    done, st, t0 = run(arrivals)
+    lat = np.array([(done[i]["t_done_ns"] - done[i]["t_arrival_ns"]) * 1e-6 for i in range(n)])
+    ok = all(done[i]["status"] == 0 for i in range(n + 1))
+    span = (max(c["t_done_ns"] for c in done.values()) - t0) * 1e-9
+    ints = int((hi - lo).sum())
+    s.close()
+    return {"workload": "2000 requests (seed 1): lo log-uniform [1e6, 1e14], length log-uniform "
+                        "[1e4, 1e9], 30% listed as uint64, Poisson arrivals; plus the count of "
+                        "[2, 1e12] at t = 0", "ok": ok,
+            "saturated_req_per_s": round(mu, 1), "lambda_req_per_s": round(lam, 1),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "mean_ms": round(float(lat.mean()), 3),
+            "long_job_ms": round((done[n]["t_done_ns"] - done[n]["t_arrival_ns"]) * 1e-6, 3),
+            "long_job_count": int(done[n]["count"]),
+            "ints_per_s": round((ints + long_hi - long_lo) / span, 1),
+            "req_per_s": round(n / span, 1),
+            "utilization": round(st["busy_ns"] / max(st["elapsed_ns"], 1), 4),
+            "steps": st["steps"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,9 +216,23 @@ def main() -> int:
     ap.add_argument("--split-hits", type=int, default=0)
     ap.add_argument("--presieve-groups", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="headline count only")
     ap.add_argument("--cpu-sample", type=int, default=10 ** 11,
                     help="integers of the oracle's timed slice (the top of the range)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (5 times), the reference "
+                         "for scaling the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(args.copy_calibration // 4, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 4, "copies": 5}), flush=True)
+        return 0
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -135,6 +280,17 @@ def main() -> int:
             "kernel": "k_sieve", "kernel_ms": round(k_ms, 4), "marks": marks,
             "algorithmic_bytes": lds_bytes}
 
+    s.close()
+    extras = None
+    if not args.no_extras:
+        from paper_2310_17746_amd import workloads
+        extras = {}
+        for name, fn in (("list_1e9", lambda: bench_list(pkg, torch, params)),
+                         ("batch_4096", lambda: bench_batch(pkg, torch, params, workloads)),
+                         ("serve_2000", lambda: bench_serve(pkg, workloads))):
+            print("bench: %s" % name, file=sys.stderr, flush=True)
+            extras[name] = fn()
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -166,9 +322,9 @@ def main() -> int:
         "count_ok": count_ok,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "extras": extras,
     }
     print(json.dumps(line), flush=True)
-    s.close()
     return 0 if count_ok is not False else 1
 
 

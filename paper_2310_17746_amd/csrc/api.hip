@@ -90,14 +90,16 @@ int hip_status(hipError_t e)
 
 void fill_defaults(sieve_params &p)
 {
+    // Defaults from the sweep on MI355X (pi(10^11) count): 48 KiB tiles, 512
+    // threads and three workgroups per CU (24 waves), work items of ~32 hits.
     if (!p.segment_bytes)
-        p.segment_bytes = 64 * 1024;
+        p.segment_bytes = 48 * 1024;
     if (!p.block_threads)
         p.block_threads = 512;
     if (!p.presieve_groups)
         p.presieve_groups = kMaxGroups;
     if (!p.split_hits)
-        p.split_hits = 256;
+        p.split_hits = 32;
     if (!p.bucket_threshold)
         p.bucket_threshold = SIEVE_BUCKET_NEVER;
     if (!p.wg_per_cu)

@@ -63,9 +63,10 @@ __device__ inline uint64_t spread32(uint32_t x)
     return v;
 }
 
-// The two planes live interleaved at LDS byte address 0: word w of A_one at
-// byte 8w, word w of A_five at byte 8w + 4.  Marks address LDS through this
-// computed byte address (the kernel checks that its dynamic LDS starts at 0).
+// The two planes live at LDS byte address 0: A_one words at bytes [0, 4PW),
+// A_five words at [4PW, 8PW).  Marks address LDS through this computed byte
+// address (the kernel checks that its dynamic LDS starts at 0).  Keeping the
+// planes apart lets the marks of one plane use every LDS bank.
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
 __device__ __forceinline__ void lds_or(uint32_t byte_addr, uint32_t mask)
@@ -73,12 +74,11 @@ __device__ __forceinline__ void lds_or(uint32_t byte_addr, uint32_t mask)
     __atomic_fetch_or((lds_u32 *)(size_t)byte_addr, mask, __ATOMIC_RELAXED);
 }
 
-// Sets the composite bits start, start + step, ... below nbits of one plane
-// (ROFF = 0 for A_one, 4 for A_five).  The paper strides by P indices in
+// Sets the composite bits start, start + step, ... below nbits of the plane
+// whose words start at LDS byte `base`.  The paper strides by P indices in
 // each array (Sec. 3: adding P to the index adds 6P to the value and keeps
 // the residue mod 6).
-template <uint32_t ROFF>
-__device__ __forceinline__ void mark_plane(uint64_t start, uint32_t step, uint32_t nbits)
+__device__ __forceinline__ void mark_plane(uint32_t base, uint64_t start, uint32_t step, uint32_t nbits)
 {
     if (start >= nbits)
         return;
@@ -90,15 +90,15 @@ __device__ __forceinline__ void mark_plane(uint64_t start, uint32_t step, uint32
             // stops the compiler from splitting it into several).
             asm volatile("" : "+v"(i));
             const uint32_t i1 = i + step, i2 = i1 + step, i3 = i2 + step;
-            lds_or(((i >> 2) & ~7u) + ROFF, 1u << (i & 31));
-            lds_or(((i1 >> 2) & ~7u) + ROFF, 1u << (i1 & 31));
-            lds_or(((i2 >> 2) & ~7u) + ROFF, 1u << (i2 & 31));
-            lds_or(((i3 >> 2) & ~7u) + ROFF, 1u << (i3 & 31));
+            lds_or(((i >> 3) & ~3u) + base, 1u << (i & 31));
+            lds_or(((i1 >> 3) & ~3u) + base, 1u << (i1 & 31));
+            lds_or(((i2 >> 3) & ~3u) + base, 1u << (i2 & 31));
+            lds_or(((i3 >> 3) & ~3u) + base, 1u << (i3 & 31));
             i = i3 + step;
         }
     }
     for (; i < nbits; i += step)
-        lds_or(((i >> 2) & ~7u) + ROFF, 1u << (i & 31));
+        lds_or(((i >> 3) & ~3u) + base, 1u << (i & 31));
 }
 
 }  // namespace
@@ -122,7 +122,9 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
     const uint32_t lane = tid & (kWave - 1);
     const uint32_t wave = tid / kWave;
     const uint32_t pw = a.pw;
-    uint2 *planes = reinterpret_cast<uint2 *>(lds);  // {A_one, A_five} word pairs
+    uint32_t *pl1 = lds;  // A_one words
+    uint32_t *pl5 = lds + pw;  // A_five words
+    const uint32_t base5 = 4 * pw;  // LDS byte address of A_five
     TileShared &sh = *reinterpret_cast<TileShared *>(lds + 2 * pw);
     const uint64_t ntiles = a.job->ntiles;
     const uint32_t nranges = a.job->nranges;
@@ -205,7 +207,8 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
                     o[g] += a.groups[g].step;
                     o[g] = o[g] >= a.groups[g].period ? o[g] - a.groups[g].period : o[g];
                 }
-                planes[w] = c;
+                pl1[w] = c.x;
+                pl5[w] = c.y;
             }
         }
         __syncthreads();
@@ -240,8 +243,8 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
                 wheel_start(pc.p, pc.r, ((uint64_t)pc.m_hi << 32) | pc.m_lo, B, M, narrow, id1, id5);
                 const uint32_t step = g * pc.p;
                 const uint32_t off = j * pc.p;
-                mark_plane<0>((uint64_t)id1 + off, step, nbits);
-                mark_plane<4>((uint64_t)id5 + off, step, nbits);
+                mark_plane(0, (uint64_t)id1 + off, step, nbits);
+                mark_plane(base5, (uint64_t)id5 + off, step, nbits);
             }
         }
         __syncthreads();
@@ -270,8 +273,7 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
         for (uint32_t w = tid; w < nw_pad; w += NT) {
             uint32_t p1 = 0, p5 = 0;
             if (w < nwords) {
-                const uint2 cw = planes[w];
-                uint32_t c1 = cw.x, c5 = cw.y;
+                uint32_t c1 = pl1[w], c5 = pl5[w];
                 if (w == 0 && B < 62) {
                     // The presieved primes themselves (5..61) lie in word 0
                     // of any tile based below 62: the patterns marked them.

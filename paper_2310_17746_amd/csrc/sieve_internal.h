@@ -1,9 +1,9 @@
 // Internal layout shared by the HIP kernels and the host runtime of libsieve.
 //
 // Value layout (Sec. 2.1, Fig. 2): a tile with value base B (a multiple of
-// 6) holds two bit planes of PW 32-bit words each in LDS, interleaved word by
-// word (A_one word w at byte 8w, A_five word w at byte 8w + 4).  Bit i of
-// plane A_r (r = 1 or 5) stands for the value B + 6*i + r.  One plane word
+// 6) holds two bit planes of PW 32-bit words each in LDS (A_one words at
+// bytes [0, 4PW), A_five words at [4PW, 8PW)).  Bit i of plane A_r (r = 1 or
+// 5) stands for the value B + 6*i + r.  One plane word
 // covers 192 consecutive integers; a tile covers 192 * PW integers.  In LDS a
 // set bit means "composite / excluded" so that marking is a single LDS OR.
 //
