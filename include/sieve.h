@@ -71,9 +71,12 @@ typedef struct sieve_ctx sieve_ctx;
  *                    default; SIEVE_PRESIEVE_NONE disables the presieve.
  *   split_hits       target hits per marking work item: primes with more
  *                    hits per tile are split over several lanes.
- *   bucket_threshold primes at least this large (and larger than a plane)
- *                    go through the bucket sieve on multi-tile ranges;
- *                    SIEVE_BUCKET_NEVER disables it.
+ *   bucket_threshold primes at least this large go through the bucket
+ *                    sieve on ranges of two or more tiles.  0 (default):
+ *                    four plane lengths (16 * segment_bytes), and only on
+ *                    ranges with at least 32768 such primes; any other
+ *                    value applies to every multi-tile range;
+ *                    SIEVE_BUCKET_NEVER disables the bucket sieve.
  *   wg_per_cu        persistent workgroups launched per compute unit.
  *   use_graph        1: batched calls replay a captured hipGraph.
  */
@@ -190,13 +193,15 @@ int sieve_plan_range(uint64_t lo, uint64_t hi, uint32_t segment_bytes, uint64_t 
 
 /*
  * Event timing of the job phases, for measurement: when on, every
- * non-graph job records the duration of its sieve kernel and of its
- * finalize + compaction kernels (HIP events on the stream the kernels run
- * on).  sieve_get_timing returns the sums in milliseconds and the number of
- * jobs timed; sieve_set_timing resets them.
+ * non-graph job records the duration of its sieve kernel, of its
+ * finalize + compaction kernels and of its bucket-sieve kernels (count,
+ * scan, fill), with HIP events on the stream the kernels run on.
+ * sieve_get_timing returns the sums in milliseconds and the number of jobs
+ * timed; sieve_set_timing resets them.
  */
 int sieve_set_timing(sieve_ctx *ctx, int on);
-int sieve_get_timing(const sieve_ctx *ctx, double *sieve_ms, double *post_ms, uint64_t *jobs);
+int sieve_get_timing(const sieve_ctx *ctx, double *sieve_ms, double *post_ms, double *bucket_ms,
+                     uint64_t *jobs);
 
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of range queries.

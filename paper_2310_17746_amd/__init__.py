@@ -118,6 +118,7 @@ def load_library():
                                             ctypes.POINTER(_u64), ctypes.POINTER(ctypes.c_uint32)]),
         "sieve_set_timing": (ctypes.c_int, [_p, ctypes.c_int]),
         "sieve_get_timing": (ctypes.c_int, [_p, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_u64)]),
         "sieve_probe_lds": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
@@ -334,10 +335,15 @@ class Sieve:
 
     def timing(self) -> tuple[float, float, int]:
         """(sieve kernel ms, finalize+compaction ms, jobs) summed since set_timing."""
-        a, b, n = ctypes.c_double(), ctypes.c_double(), _u64()
-        _check(self._lib.sieve_get_timing(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)),
-               "sieve_get_timing")
-        return a.value, b.value, n.value
+        a, b, c, n = self.timing_all()
+        return a, b, n
+
+    def timing_all(self) -> tuple[float, float, float, int]:
+        """(sieve ms, finalize+compaction ms, bucket-sieve ms, jobs) since set_timing."""
+        a, b, c, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), _u64()
+        _check(self._lib.sieve_get_timing(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                          ctypes.byref(n)), "sieve_get_timing")
+        return a.value, b.value, c.value, n.value
 
 
 class Server:

@@ -22,7 +22,9 @@
 namespace sieve {
 hipError_t set_sieve_lds_limit(uint32_t bytes);
 hipError_t launch_zero(const JobHeader *job, unsigned long long *counters, unsigned long long *counts,
-                       hipStream_t s);
+                       uint32_t *bcount, hipStream_t s);
+hipError_t launch_bucket(const BucketArgs &a, int pass, uint32_t grid, hipStream_t s);
+hipError_t launch_bucket_scan(const BucketScanArgs &a, hipStream_t s);
 hipError_t launch_sieve(const SieveArgs &a, uint32_t nt, uint32_t grid, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs &a, uint32_t grid, hipStream_t s);
 hipError_t launch_compact(const CompactArgs &a, uint32_t grid, hipStream_t s);
@@ -100,8 +102,6 @@ void fill_defaults(sieve_params &p)
         p.presieve_groups = kMaxGroups;
     if (!p.split_hits)
         p.split_hits = 32;
-    if (!p.bucket_threshold)
-        p.bucket_threshold = SIEVE_BUCKET_NEVER;
     if (!p.wg_per_cu)
         p.wg_per_cu = std::max<uint32_t>(1, std::min<uint32_t>(4, (160 * 1024) / p.segment_bytes));
 }
@@ -230,6 +230,14 @@ int install_primes(sieve_ctx *c, uint64_t limit)
         e = hipMemcpy(c->d_item_prefix.p, prefix.data(), prefix.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e != hipSuccess)
         return hip_status(e);
+    // Bucket sieve: primes at least the threshold (default four plane lengths,
+    // where a prime hits a given tile with probability below 1/2).
+    const uint64_t thr = c->prm.bucket_threshold ? (uint64_t)c->prm.bucket_threshold : 4 * plane_bits;
+    uint32_t kl = (uint32_t)n;
+    if (c->prm.bucket_threshold != SIEVE_BUCKET_NEVER)
+        kl = (uint32_t)(std::lower_bound(P.begin(), P.end(), (uint32_t)std::min<uint64_t>(thr, 0xFFFFFFFFull)) -
+                        P.begin());
+    c->k_large = std::max(kl, ks);
     c->limit = limit;
     c->first_mark = fm;
     c->k_split = ks;
@@ -256,7 +264,7 @@ struct Plan {
     std::vector<RangeDesc> ranges;
     std::vector<uint32_t> list_idx;
     std::vector<uint64_t> list_chunk0;
-    uint64_t ntiles = 0, nchunks = 0;
+    uint64_t ntiles = 0, nchunks = 0, nunits = 0;
 };
 
 int make_plan(const sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, const uint8_t *mode,
@@ -284,6 +292,22 @@ int make_plan(const sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t
         d.ntiles = (uint32_t)nt;
         d.tile0 = pl.ntiles;
         pl.ntiles += nt;
+        // Base primes with p * p < hi; on multi-tile ranges the ones from
+        // k_large on go through the bucket sieve.
+        d.nact = b > 4 ? (uint32_t)(std::upper_bound(c->h_primes.begin(), c->h_primes.end(),
+                                                     (uint32_t)isqrt_host(b - 1)) -
+                                    c->h_primes.begin())
+                       : 0u;
+        // A range takes the bucket sieve when it spans several tiles and its
+        // large primes are many: each then costs one start per tile window
+        // instead of one per tile, and only its actual hits are walked.
+        // (An explicit threshold applies to every multi-tile range.)
+        const uint32_t min_large = c->prm.bucket_threshold ? 1u : kBucketMinPrimes;
+        d.kbig = (nt >= 2 && d.nact >= c->k_large + min_large) ? c->k_large : d.nact;
+        d.bwins = (uint32_t)((nt + kBucketWindow - 1) / kBucketWindow);
+        d.bunits = d.kbig < d.nact ? ((d.nact - d.kbig + kBucketThreads - 1) / kBucketThreads) * d.bwins : 0;
+        d.bunit0 = pl.nunits;
+        pl.nunits += d.bunits;
         d.mode = lst ? 1u : 0u;
         if (lst) {
             d.out_off = off ? off[i] : 0;
@@ -326,8 +350,8 @@ uint64_t grow(uint64_t cur, uint64_t need, uint64_t floor_)
 }
 
 // Makes the scratch hold a job of the given size.  Capacities only grow; any
-// reallocation bumps c->gen so that a captured graph is re-made.
-int ensure_capacity(sieve_ctx *c, uint64_t nranges, uint64_t nlist, uint64_t nchunks)
+// reallocation bumps c->gen so that captured graphs are re-made.
+int ensure_capacity(sieve_ctx *c, uint64_t nranges, uint64_t nlist, uint64_t nchunks, uint64_t ntiles)
 {
     bool changed = false;
     if (nranges > c->cap_ranges || nlist > c->cap_list || !c->d_blob.p) {
@@ -370,11 +394,27 @@ int ensure_capacity(sieve_ctx *c, uint64_t nranges, uint64_t nlist, uint64_t nch
             return SIEVE_E_NOMEM;
         changed = true;
     }
+    if (ntiles > c->cap_tiles || !c->d_bcount.p) {
+        c->cap_tiles = grow(c->cap_tiles, ntiles, 1024);
+        c->d_bcount.release();
+        c->d_bcursor.release();
+        c->d_boff.release();
+        if (!c->d_bcount.reserve(c->cap_tiles) || !c->d_bcursor.reserve(c->cap_tiles) ||
+            !c->d_boff.reserve(c->cap_tiles + 1))
+            return SIEVE_E_NOMEM;
+        changed = true;
+    }
+    if (!c->d_bdata.p) {
+        c->cap_bdata = 1024;
+        if (!c->d_bdata.reserve(c->cap_bdata))
+            return SIEVE_E_NOMEM;
+        changed = true;
+    }
     if (!c->d_counters.p) {
         if (!c->d_counters.reserve(kNumCounters))
             return SIEVE_E_NOMEM;
-        if (!c->h_flag && hipHostMalloc((void **)&c->h_flag, sizeof(unsigned long long), hipHostMallocDefault) !=
-                              hipSuccess) {
+        if (hipHostMalloc((void **)&c->h_flag, sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&c->h_btotal, sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
             return SIEVE_E_NOMEM;
         }
@@ -385,17 +425,60 @@ int ensure_capacity(sieve_ctx *c, uint64_t nranges, uint64_t nlist, uint64_t nch
     return SIEVE_OK;
 }
 
-// Enqueues the job kernels on stream s; also used under graph capture.  All
-// job-specific values are read by the kernels from the device blob, whose
-// layout depends only on the capacities.
-hipError_t enqueue_kernels(sieve_ctx *c, hipStream_t s, bool timed)
+enum Phase { kPhaseWhole = 0, kPhaseBucketCount = 1, kPhaseRest = 2 };
+
+// Enqueues one phase of the job kernels on stream s; also used under graph
+// capture.  All job-specific values are read by the kernels from the device
+// blob, whose layout depends only on the capacities.
+//   whole:         zero, sieve, finalize, compact       (jobs without buckets)
+//   bucket count:  zero, bucket count, bucket scan
+//   rest:          bucket fill, sieve, finalize, compact
+hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed)
 {
     const BlobLayout L = blob_layout(c->cap_ranges, c->cap_list);
     const JobHeader *job = (const JobHeader *)c->d_blob.p;
     const RangeDesc *ranges = (const RangeDesc *)(c->d_blob.p + L.ranges);
-    hipError_t e = launch_zero(job, c->d_counters.p, c->d_counts.p, s);
-    if (e != hipSuccess)
-        return e;
+    const uint32_t pw = c->prm.segment_bytes / 8;
+    hipError_t e = hipSuccess;
+    BucketArgs b;
+    memset(&b, 0, sizeof b);
+    b.job = job;
+    b.ranges = ranges;
+    b.prm = c->d_prm.p;
+    b.bcount = c->d_bcount.p;
+    b.bcursor = c->d_bcursor.p;
+    b.boff = c->d_boff.p;
+    b.bdata = c->d_bdata.p;
+    b.nbits = 32 * pw;
+    b.span = 192ull * pw;
+    b.span_rcp = UINT64_MAX / b.span;
+    const uint32_t bgrid = (uint32_t)c->cus * 8;
+    if (phase != kPhaseRest) {
+        if (timed && phase == kPhaseBucketCount && (e = hipEventRecord(c->ev[3], s)) != hipSuccess)
+            return e;
+        if ((e = launch_zero(job, c->d_counters.p, c->d_counts.p, c->d_bcount.p, s)) != hipSuccess)
+            return e;
+    }
+    if (phase == kPhaseBucketCount) {
+        if ((e = launch_bucket(b, 0, bgrid, s)) != hipSuccess)
+            return e;
+        BucketScanArgs sc;
+        sc.job = job;
+        sc.bcount = c->d_bcount.p;
+        sc.boff = c->d_boff.p;
+        sc.bcursor = c->d_bcursor.p;
+        if ((e = launch_bucket_scan(sc, s)) != hipSuccess)
+            return e;
+        if (timed && (e = hipEventRecord(c->ev[4], s)) != hipSuccess)
+            return e;
+        return hipSuccess;
+    }
+    if (phase == kPhaseRest) {
+        if (timed && (e = hipEventRecord(c->ev[5], s)) != hipSuccess)
+            return e;
+        if ((e = launch_bucket(b, 1, bgrid, s)) != hipSuccess)
+            return e;
+    }
     SieveArgs a;
     memset(&a, 0, sizeof a);
     a.job = job;
@@ -416,9 +499,12 @@ hipError_t enqueue_kernels(sieve_ctx *c, hipStream_t s, bool timed)
     a.ngroups = c->ngroups;
     a.restore1 = c->restore1;
     a.restore5 = c->restore5;
-    a.pw = c->prm.segment_bytes / 8;
+    a.pw = pw;
     a.bitmap = c->d_bitmap.p;
     a.chunk_counts = c->d_chunk_counts.p;
+    a.bdata = c->d_bdata.p;
+    a.boff = c->d_boff.p;
+    a.bcount = c->d_bcount.p;
     if (timed && (e = hipEventRecord(c->ev[0], s)) != hipSuccess)
         return e;
     e = launch_sieve(a, c->prm.block_threads, (uint32_t)c->cus * c->prm.wg_per_cu, s);
@@ -450,30 +536,46 @@ hipError_t enqueue_kernels(sieve_ctx *c, hipStream_t s, bool timed)
     return hipSuccess;
 }
 
-hipError_t capture_graph(sieve_ctx *c)
+hipError_t capture_graph(sieve_ctx *c, int phase)
 {
-    if (c->graph) {
-        (void)hipGraphExecDestroy(c->graph);
-        c->graph = nullptr;
+    if (c->graph[phase]) {
+        (void)hipGraphExecDestroy(c->graph[phase]);
+        c->graph[phase] = nullptr;
     }
-    if (c->graph_src) {
-        (void)hipGraphDestroy(c->graph_src);
-        c->graph_src = nullptr;
+    if (c->graph_src[phase]) {
+        (void)hipGraphDestroy(c->graph_src[phase]);
+        c->graph_src[phase] = nullptr;
     }
     hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess)
         return e;
-    hipError_t e2 = enqueue_kernels(c, c->stream, false);
-    e = hipStreamEndCapture(c->stream, &c->graph_src);
+    hipError_t e2 = enqueue_phase(c, c->stream, phase, false);
+    e = hipStreamEndCapture(c->stream, &c->graph_src[phase]);
     if (e2 != hipSuccess)
         return e2;
     if (e != hipSuccess)
         return e;
-    e = hipGraphInstantiate(&c->graph, c->graph_src, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&c->graph[phase], c->graph_src[phase], nullptr, nullptr, 0);
     if (e != hipSuccess)
         return e;
-    c->graph_gen = c->gen;
+    c->graph_gen[phase] = c->gen;
     return hipSuccess;
+}
+
+// Runs one phase on stream s, directly or by replaying its graph.
+hipError_t run_phase(sieve_ctx *c, hipStream_t s, int phase, bool use_graph)
+{
+    if (!use_graph)
+        return enqueue_phase(c, s, phase, c->timing != 0);
+    hipError_t e;
+    if (!c->graph[phase] || c->graph_gen[phase] != c->gen) {
+        // Capture on the context stream once the work before it is done.
+        if (s != c->stream && (e = hipStreamSynchronize(s)) != hipSuccess)
+            return e;
+        if ((e = capture_graph(c, phase)) != hipSuccess)
+            return e;
+    }
+    return hipGraphLaunch(c->graph[phase], s);
 }
 
 // Runs one job: plan, upload, kernels (graph or direct), results.
@@ -489,7 +591,7 @@ int run_job(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, co
     const uint64_t nlist = pl.list_idx.size();
     if (nlist && !out)
         return SIEVE_E_INVAL;
-    st = ensure_capacity(c, n, nlist, pl.nchunks);
+    st = ensure_capacity(c, n, nlist, pl.nchunks, pl.ntiles);
     if (st != SIEVE_OK)
         return st;
     hipStream_t s = stream ? stream : c->stream;
@@ -498,6 +600,7 @@ int run_job(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, co
     memset(h, 0, sizeof *h);
     h->ntiles = pl.ntiles;
     h->nchunks = pl.nchunks;
+    h->nunits = pl.nunits;
     h->nranges = (uint32_t)n;
     h->nlist = (uint32_t)nlist;
     h->out = out;
@@ -515,19 +618,28 @@ int run_job(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, co
                            L.list_chunk0 - L.list_idx + nlist * sizeof(uint64_t), hipMemcpyHostToDevice, s);
     if (e != hipSuccess)
         return hip_status(e);
-    if (use_graph) {
-        if (!c->graph || c->graph_gen != c->gen) {
-            // Capture on the context stream after the uploads are ordered.
-            if (s != c->stream) {
-                if ((e = hipStreamSynchronize(s)) != hipSuccess)
-                    return hip_status(e);
-            }
-            if ((e = capture_graph(c)) != hipSuccess)
-                return hip_status(e);
+    const bool buckets = pl.nunits != 0;
+    if (buckets) {
+        // Count the bucket entries, then size the entry store exactly.
+        if ((e = run_phase(c, s, kPhaseBucketCount, use_graph)) != hipSuccess)
+            return hip_status(e);
+        e = hipMemcpyAsync(c->h_btotal, c->d_boff.p + pl.ntiles, sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (e != hipSuccess)
+            return hip_status(e);
+        const uint64_t total = *c->h_btotal;
+        if (total > c->cap_bdata) {
+            c->cap_bdata = grow(c->cap_bdata, total, 1024);
+            c->d_bdata.release();
+            if (!c->d_bdata.reserve(c->cap_bdata))
+                return SIEVE_E_NOMEM;
+            c->gen++;
         }
-        e = hipGraphLaunch(c->graph, s);
+        e = run_phase(c, s, kPhaseRest, use_graph);
     } else {
-        e = enqueue_kernels(c, s, c->timing != 0);
+        e = run_phase(c, s, kPhaseWhole, use_graph);
     }
     if (e != hipSuccess)
         return hip_status(e);
@@ -547,13 +659,16 @@ int run_job(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, co
     if (*c->h_flag)
         return SIEVE_E_DEVICE;  // a kernel refused to run (see its error flag)
     if (c->timing && !use_graph) {
-        float a = 0, b = 0;
+        float a = 0, b = 0, bc = 0, bf = 0;
         if (hipEventElapsedTime(&a, c->ev[0], c->ev[1]) == hipSuccess &&
             hipEventElapsedTime(&b, c->ev[1], c->ev[2]) == hipSuccess) {
             c->t_sieve_ms += a;
             c->t_post_ms += b;
             c->t_jobs++;
         }
+        if (buckets && hipEventElapsedTime(&bc, c->ev[3], c->ev[4]) == hipSuccess &&
+            hipEventElapsedTime(&bf, c->ev[5], c->ev[0]) == hipSuccess)
+            c->t_bucket_ms += bc + bf;
     }
     for (uint64_t i = 0; i < n; ++i) {
         if (counts)
@@ -607,10 +722,18 @@ void destroy_ctx(sieve_ctx *c)
 {
     if (!c)
         return;
-    if (c->graph)
-        (void)hipGraphExecDestroy(c->graph);
-    if (c->graph_src)
-        (void)hipGraphDestroy(c->graph_src);
+    for (int g = 0; g < 3; ++g) {
+        if (c->graph[g])
+            (void)hipGraphExecDestroy(c->graph[g]);
+        if (c->graph_src[g])
+            (void)hipGraphDestroy(c->graph_src[g]);
+    }
+    c->d_bcount.release();
+    c->d_bcursor.release();
+    c->d_bdata.release();
+    c->d_boff.release();
+    if (c->h_btotal)
+        (void)hipHostFree(c->h_btotal);
     c->d_prm.release();
     c->d_pidx.release();
     c->d_items.release();
@@ -753,7 +876,7 @@ int sieve_create(sieve_ctx **out, int device, const sieve_params *p)
     if (st == SIEVE_OK)
         st = install_primes(c, 0);
     if (st == SIEVE_OK)
-        st = ensure_capacity(c, 1, 1, 1);
+        st = ensure_capacity(c, 1, 1, 1, 1);
     if (st != SIEVE_OK) {
         destroy_ctx(c);
         return st;
@@ -926,17 +1049,18 @@ int sieve_set_timing(sieve_ctx *ctx, int on)
     if (!ctx)
         return SIEVE_E_INVAL;
     ctx->timing = on;
-    ctx->t_sieve_ms = ctx->t_post_ms = 0;
+    ctx->t_sieve_ms = ctx->t_post_ms = ctx->t_bucket_ms = 0;
     ctx->t_jobs = 0;
     return SIEVE_OK;
 }
 
-int sieve_get_timing(const sieve_ctx *ctx, double *sieve_ms, double *post_ms, uint64_t *jobs)
+int sieve_get_timing(const sieve_ctx *ctx, double *sieve_ms, double *post_ms, double *bucket_ms, uint64_t *jobs)
 {
-    if (!ctx || !sieve_ms || !post_ms || !jobs)
+    if (!ctx || !sieve_ms || !post_ms || !bucket_ms || !jobs)
         return SIEVE_E_INVAL;
     *sieve_ms = ctx->t_sieve_ms;
     *post_ms = ctx->t_post_ms;
+    *bucket_ms = ctx->t_bucket_ms;
     *jobs = ctx->t_jobs;
     return SIEVE_OK;
 }

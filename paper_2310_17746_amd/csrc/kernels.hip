@@ -215,7 +215,8 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
 
         // ---- marking: Table 1 starts, stride P in each plane -------------
         {
-            const uint32_t n_act = sh.nact;
+            // Primes from d.kbig on come from this tile's bucket instead.
+            const uint32_t n_act = sh.nact < d.kbig ? sh.nact : d.kbig;
             const uint32_t ks = n_act < a.k_split ? n_act : a.k_split;
             const uint32_t n_items = ks > a.first_mark ? a.item_prefix[ks - a.first_mark] : 0;
             const uint32_t n_rest = n_act > a.k_split ? n_act - a.k_split : 0;
@@ -245,6 +246,15 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
                 const uint32_t off = j * pc.p;
                 mark_plane(0, (uint64_t)id1 + off, step, nbits);
                 mark_plane(base5, (uint64_t)id5 + off, step, nbits);
+            }
+            // Bucket entries of this tile: one mark each.
+            if (d.kbig < d.nact) {
+                const uint64_t e0 = a.boff[t], ne = a.bcount[t];
+                for (uint64_t e = tid; e < ne; e += NT) {
+                    const uint32_t v = a.bdata[e0 + e];
+                    const uint32_t bit = v & 0x7FFFFFFFu;
+                    lds_or(((bit >> 3) & ~3u) + ((v >> 31) ? base5 : 0u), 1u << (bit & 31));
+                }
             }
         }
         __syncthreads();
@@ -321,6 +331,199 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
         }
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------------------
+// Bucket sieve.  For a range of several tiles, a prime far above the plane
+// length hits a given tile with small probability, so instead of a Table 1
+// start per (tile, prime) it gets one start per range and its hits are
+// walked tile by tile: each hit advances by (P div nbits) tiles and
+// (P mod nbits) bits.  Hits are binned per tile in LDS windows of
+// kBucketWindow tiles.  The count pass adds the per-tile totals; after a
+// scan, the fill pass reserves each tile's slice with one global atomic per
+// (workgroup, tile) and writes the entries (bit | plane << 31).
+// ---------------------------------------------------------------------------
+namespace {
+
+struct HitWalk {
+    uint32_t t1, b1, t5, b5;  // next hit (tile, bit) per plane; t = ntiles when done
+    uint32_t qp, rp;          // P div nbits, P mod nbits
+};
+
+__device__ inline void walk_step(uint32_t &t, uint32_t &b, const HitWalk &w, uint32_t nbits)
+{
+    b += w.rp;
+    t += w.qp;
+    if (b >= nbits) {
+        b -= nbits;
+        t += 1;
+    }
+}
+
+// First hits of prime k in tiles [w0, wend) of range d (tile indices
+// relative to the range's tile 0; t = wend when there is none).
+__device__ inline HitWalk walk_init(const BucketArgs &a, const RangeDesc &d, uint32_t k, uint32_t w0,
+                                    uint32_t wend)
+{
+    HitWalk w;
+    w.t1 = w.t5 = wend;
+    w.b1 = w.b5 = 0;
+    w.qp = w.rp = 0;
+    if (k >= d.nact)
+        return w;
+    const PrimeConst pc = a.prm[k];
+    const uint64_t P = pc.p;
+    const uint64_t P2 = P * P;
+    const uint64_t wbase = d.base + (uint64_t)w0 * a.span;
+    const uint64_t M = P2 > wbase ? P2 : wbase;
+    const uint64_t rend = d.base + (uint64_t)wend * a.span;
+    if (M >= rend)
+        return w;
+    // tile holding M, by the reciprocal of the tile span
+    const uint64_t x = M - d.base;
+    uint64_t tM = mulhi64(x, a.span_rcp);
+    if (x - tM * a.span >= a.span)
+        ++tM;
+    const uint64_t Bt = d.base + tM * a.span;
+    uint32_t id1, id5;
+    wheel_start(pc.p, pc.r, ((uint64_t)pc.m_hi << 32) | pc.m_lo, Bt, M, rend <= (1ull << 62), id1, id5);
+    w.qp = pc.p / a.nbits;
+    w.rp = pc.p - w.qp * a.nbits;
+    const uint64_t t1 = tM + id1 / a.nbits, t5 = tM + id5 / a.nbits;
+    w.t1 = t1 < wend ? (uint32_t)t1 : wend;
+    w.b1 = id1 % a.nbits;
+    w.t5 = t5 < wend ? (uint32_t)t5 : wend;
+    w.b5 = id5 % a.nbits;
+    return w;
+}
+
+__device__ inline uint32_t find_unit_range(const RangeDesc *ranges, uint32_t nranges, uint64_t u)
+{
+    uint32_t lo = 0, hi = nranges;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (ranges[mid].bunit0 <= u)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+}  // namespace
+
+template <int PASS>
+__global__ void __launch_bounds__(kBucketThreads) k_bucket(BucketArgs a)
+{
+    __shared__ uint32_t s_cnt[kBucketWindow];
+    __shared__ uint32_t s_cur[PASS ? kBucketWindow : 1];
+    __shared__ unsigned long long s_base[PASS ? kBucketWindow : 1];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t nunits = a.job->nunits;
+    const uint32_t nranges = a.job->nranges;
+    const uint32_t nbits = a.nbits;
+
+    for (uint64_t u = blockIdx.x; u < nunits; u += gridDim.x) {
+        const uint32_t r = find_unit_range(a.ranges, nranges, u);
+        const RangeDesc &d = a.ranges[r];
+        // unit = (prime block, tile window) of range r
+        const uint32_t ur = (uint32_t)(u - d.bunit0);
+        const uint32_t blk = ur / d.bwins, win = ur - blk * d.bwins;
+        const uint32_t w0 = win * kBucketWindow;
+        const uint32_t wend = (d.ntiles - w0) < kBucketWindow ? d.ntiles : w0 + kBucketWindow;
+        const uint32_t k = d.kbig + blk * kBucketThreads + tid;
+        HitWalk w = walk_init(a, d, k, w0, wend);
+        for (uint32_t i = tid; i < wend - w0; i += kBucketThreads) {
+            s_cnt[i] = 0;
+            if (PASS)
+                s_cur[i] = 0;
+        }
+        __syncthreads();
+        if (PASS == 0) {
+            while (w.t1 < wend) {
+                atomicAdd(&s_cnt[w.t1 - w0], 1u);
+                walk_step(w.t1, w.b1, w, nbits);
+            }
+            while (w.t5 < wend) {
+                atomicAdd(&s_cnt[w.t5 - w0], 1u);
+                walk_step(w.t5, w.b5, w, nbits);
+            }
+            __syncthreads();
+            for (uint32_t i = tid; i < wend - w0; i += kBucketThreads)
+                if (s_cnt[i])
+                    atomicAdd(&a.bcount[d.tile0 + w0 + i], s_cnt[i]);
+        } else {
+            {
+                HitWalk c = w;  // count first, without moving the walk
+                while (c.t1 < wend) {
+                    atomicAdd(&s_cnt[c.t1 - w0], 1u);
+                    walk_step(c.t1, c.b1, c, nbits);
+                }
+                while (c.t5 < wend) {
+                    atomicAdd(&s_cnt[c.t5 - w0], 1u);
+                    walk_step(c.t5, c.b5, c, nbits);
+                }
+            }
+            __syncthreads();
+            for (uint32_t i = tid; i < wend - w0; i += kBucketThreads) {
+                const uint32_t n = s_cnt[i];
+                if (n) {
+                    const uint64_t g = d.tile0 + w0 + i;
+                    s_base[i] = a.boff[g] + atomicAdd(&a.bcursor[g], n);
+                }
+            }
+            __syncthreads();
+            while (w.t1 < wend) {
+                const uint32_t slot = atomicAdd(&s_cur[w.t1 - w0], 1u);
+                a.bdata[s_base[w.t1 - w0] + slot] = w.b1;
+                walk_step(w.t1, w.b1, w, nbits);
+            }
+            while (w.t5 < wend) {
+                const uint32_t slot = atomicAdd(&s_cur[w.t5 - w0], 1u);
+                a.bdata[s_base[w.t5 - w0] + slot] = w.b5 | 0x80000000u;
+                walk_step(w.t5, w.b5, w, nbits);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Exclusive scan of the per-tile bucket counts (one workgroup); also clears
+// the fill-pass cursors.
+__global__ void __launch_bounds__(kFinalizeThreads) k_bucket_scan(BucketScanArgs a)
+{
+    __shared__ uint32_t s_w[kFinalizeThreads / kWave];
+    __shared__ unsigned long long s_carry;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & (kWave - 1);
+    const uint32_t wave = tid / kWave;
+    const uint64_t n = a.job->ntiles;
+    if (tid == 0)
+        s_carry = 0;
+    __syncthreads();
+    for (uint64_t b0 = 0; b0 < n; b0 += kFinalizeThreads) {
+        const uint64_t i = b0 + tid;
+        const uint32_t c = i < n ? a.bcount[i] : 0u;
+        const uint32_t incl = wave_incl_scan(c, lane);
+        if (lane == kWave - 1)
+            s_w[wave] = incl;
+        __syncthreads();
+        uint32_t woff = 0, btot = 0;
+        for (uint32_t q = 0; q < kFinalizeThreads / kWave; ++q) {
+            woff += q < wave ? s_w[q] : 0u;
+            btot += s_w[q];
+        }
+        if (i < n) {
+            a.boff[i] = s_carry + woff + incl - c;
+            a.bcursor[i] = 0;
+        }
+        __syncthreads();
+        if (tid == 0)
+            s_carry += btot;
+        __syncthreads();
+    }
+    if (tid == 0)
+        a.boff[n] = s_carry;
 }
 
 __global__ void __launch_bounds__(kFinalizeThreads) k_finalize(FinalizeArgs a)
@@ -463,7 +666,8 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(CompactArgs a)
     }
 }
 
-__global__ void k_zero(const JobHeader *job, unsigned long long *counters, unsigned long long *counts)
+__global__ void k_zero(const JobHeader *job, unsigned long long *counters, unsigned long long *counts,
+                       uint32_t *bcount)
 {
     const uint32_t n = job->nranges;
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -471,6 +675,9 @@ __global__ void k_zero(const JobHeader *job, unsigned long long *counters, unsig
         counters[g] = 0;
     for (uint32_t i = g; i < n; i += gridDim.x * blockDim.x)
         counts[i] = 0;
+    if (job->nunits)
+        for (uint64_t i = g; i < job->ntiles; i += gridDim.x * blockDim.x)
+            bcount[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -490,9 +697,24 @@ hipError_t set_sieve_lds_limit(uint32_t segment_bytes)
 }
 
 hipError_t launch_zero(const JobHeader *job, unsigned long long *counters, unsigned long long *counts,
-                       hipStream_t s)
+                       uint32_t *bcount, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_zero, dim3(64), dim3(256), 0, s, job, counters, counts);
+    hipLaunchKernelGGL(k_zero, dim3(256), dim3(256), 0, s, job, counters, counts, bcount);
+    return hipGetLastError();
+}
+
+hipError_t launch_bucket(const BucketArgs &a, int pass, uint32_t grid, hipStream_t s)
+{
+    if (pass == 0)
+        hipLaunchKernelGGL(k_bucket<0>, dim3(grid), dim3(kBucketThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_bucket<1>, dim3(grid), dim3(kBucketThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_bucket_scan(const BucketScanArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(kFinalizeThreads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -70,6 +70,7 @@ struct sieve_ctx {
     sieve::rt::DevBuf<uint2> d_items;
     sieve::rt::DevBuf<uint32_t> d_item_prefix;
     uint32_t first_mark = 0, k_split = 0;
+    uint32_t k_large = 0;  // first prime index the bucket sieve takes (multi-tile ranges)
 
     // Presieve tables.
     sieve::rt::DevBuf<uint2> d_pstab;
@@ -92,16 +93,24 @@ struct sieve_ctx {
     unsigned long long *h_flag = nullptr;    // pinned copy of the kernels' error flag
     uint64_t cap_ranges = 0, cap_list = 0, cap_chunks = 0;
 
-    // Graph of the job kernels; valid while gen == graph_gen.
-    hipGraphExec_t graph = nullptr;
-    hipGraph_t graph_src = nullptr;
-    uint64_t graph_gen = ~0ull;
+    // Bucket sieve scratch: per-tile counts, cursors and offsets; entries.
+    sieve::rt::DevBuf<uint32_t> d_bcount, d_bcursor, d_bdata;
+    sieve::rt::DevBuf<unsigned long long> d_boff;
+    unsigned long long *h_btotal = nullptr;  // pinned
+    uint64_t cap_tiles = 0, cap_bdata = 0;
+
+    // Graphs of the job phases (0: whole job without buckets, 1: bucket
+    // count + scan, 2: bucket fill + sieve + finalize + compact); each is
+    // valid while gen == graph_gen[i].
+    hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
+    hipGraph_t graph_src[3] = {nullptr, nullptr, nullptr};
+    uint64_t graph_gen[3] = {~0ull, ~0ull, ~0ull};
     uint64_t gen = 0;
 
     // Optional event timing of the sieve kernel and the post-processing.
     int timing = 0;
-    hipEvent_t ev[3]{};
-    double t_sieve_ms = 0, t_post_ms = 0;
+    hipEvent_t ev[6]{};
+    double t_sieve_ms = 0, t_post_ms = 0, t_bucket_ms = 0;
     uint64_t t_jobs = 0;
 };
 

@@ -29,6 +29,9 @@ constexpr int kMaxGroups = 5;                               // presieve pattern 
 constexpr uint32_t kCompactThreads = 512;                   // one bitmap word per thread
 constexpr uint32_t kStagePerWave = 512;                     // compaction staging entries per wave
 constexpr uint32_t kFinalizeThreads = 1024;
+constexpr uint32_t kBucketThreads = 256;    // primes per bucket work unit
+constexpr uint32_t kBucketWindow = 2048;    // tiles per bucket work unit (LDS bins)
+constexpr uint32_t kBucketMinPrimes = 32768; // fewest large primes worth a bucket pass
 
 // One range of a job.  Host-computed plan; read-only on the device.
 struct RangeDesc {
@@ -42,6 +45,11 @@ struct RangeDesc {
     uint32_t last_words; // plane words of the last tile
     uint32_t mode;       // 0 count, 1 list
     uint32_t nchunks;    // list ranges: bitmap chunks
+    uint32_t nact;       // resident primes p with p * p < hi
+    uint32_t kbig;       // first prime index handled by the bucket sieve (nact: none)
+    uint64_t bunit0;     // first bucket work unit of this range
+    uint32_t bunits;     // bucket work units: prime blocks x tile windows
+    uint32_t bwins;      // tile windows of kBucketWindow tiles
 };
 
 // Per-job scalars, in device memory so that a captured graph can be replayed
@@ -49,6 +57,7 @@ struct RangeDesc {
 struct JobHeader {
     uint64_t ntiles;     // tiles over all ranges
     uint64_t nchunks;    // bitmap chunks over all list ranges
+    uint64_t nunits;     // bucket work units over all ranges
     uint32_t nranges;
     uint32_t nlist;      // list ranges
     void *out;           // caller's output buffer (list ranges)
@@ -92,6 +101,32 @@ struct SieveArgs {
     uint32_t pw;                  // plane words per tile
     unsigned long long *bitmap;   // list scratch (u64 words)
     uint32_t *chunk_counts;       // per chunk prime count
+    const uint32_t *bdata;        // bucket entries: bit | plane << 31
+    const unsigned long long *boff;  // per tile: first entry
+    const uint32_t *bcount;       // per tile: entries
+};
+
+// Bucket sieve (large primes of multi-tile ranges).  One work unit is a block
+// of kBucketThreads primes of one range; every thread walks one prime's hits
+// through the range's tiles.
+struct BucketArgs {
+    const JobHeader *job;
+    const RangeDesc *ranges;
+    const PrimeConst *prm;
+    uint32_t *bcount;             // per tile (count pass: accumulated)
+    uint32_t *bcursor;            // per tile (fill pass: reserved so far)
+    const unsigned long long *boff;
+    uint32_t *bdata;
+    uint32_t nbits;               // bits per plane per tile (32 * pw)
+    uint64_t span;                // integers per tile (192 * pw)
+    uint64_t span_rcp;            // floor((2^64 - 1) / span)
+};
+
+struct BucketScanArgs {
+    const JobHeader *job;
+    const uint32_t *bcount;
+    unsigned long long *boff;     // ntiles + 1 entries; boff[ntiles] = total
+    uint32_t *bcursor;            // zeroed here for the fill pass
 };
 
 struct FinalizeArgs {

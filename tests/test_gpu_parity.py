@@ -194,6 +194,8 @@ def test_error_paths(sv):
     dict(segment_bytes=159744, block_threads=512, split_hits=64),
     dict(segment_bytes=65536, block_threads=512, presieve_groups=pkg.PRESIEVE_NONE),
     dict(segment_bytes=49152, block_threads=256, presieve_groups=3, split_hits=2048),
+    dict(segment_bytes=16384, bucket_threshold=70000),          # most primes through buckets
+    dict(segment_bytes=49152, bucket_threshold=pkg.BUCKET_NEVER),  # no bucket sieve
 ])
 def test_parameter_grid_parity(params):
     with pkg.Sieve(0, params) as s:
@@ -212,3 +214,27 @@ def test_base_primes_match_oracle(sv):
         assert n == len(oracle.simple_primes(10 ** 7)) - 2  # primes >= 5
         lo, hi = 10 ** 13, 10 ** 13 + 10 ** 6
         assert s.count(lo, hi) == oracle.count(lo, hi)
+
+
+@pytest.mark.parametrize("thr", [0, 200_000, pkg.BUCKET_NEVER])
+def test_bucket_sieve_long_ranges_at_1e15(thr):
+    """Multi-tile ranges near 10^15 with primes up to 3.2e7: bucketed and
+    per-tile paths agree with the oracle and with each other."""
+    rng = np.random.default_rng(21)
+    lo = (10 ** 15 - np.floor(10 ** rng.uniform(7, 14, 12))).astype(np.uint64)
+    hi = lo + np.floor(10 ** rng.uniform(6, 7.7, 12)).astype(np.uint64)
+    lo[0], hi[0] = 10 ** 15 - 3 * 10 ** 7, 10 ** 15  # many tiles, hi at the top
+    mode = (np.arange(12) % 2).astype(np.uint8)
+    with pkg.Sieve(0, dict(bucket_threshold=thr)) as s:
+        s.ensure_base_for(int(hi.max()))
+        cap = np.array([pkg.list_bound(int(a), int(b)) for a, b in zip(lo, hi)], dtype=np.uint64)
+        off = np.concatenate([[0], np.cumsum(cap)[:-1]]).astype(np.uint64)
+        out = torch.empty(int(cap.sum()), dtype=torch.int64, device="cuda")
+        counts, status = s.list_batch(lo, hi, mode, out, off, cap, elem_bytes=8)
+        host = _u(out, 8)
+        for i in range(12):
+            want = oracle.primes(int(lo[i]), int(hi[i]), elem_bytes=8)
+            assert status[i] == 0 and int(counts[i]) == len(want), (thr, i)
+            if mode[i]:
+                assert np.array_equal(host[int(off[i]):int(off[i]) + len(want)], want), (thr, i)
+        assert s.count(int(lo[0]), int(hi[0])) == int(counts[0])
