@@ -12,7 +12,7 @@ written per plane-word pair at init and 8 bytes read back by the popcount)
 over its average duration, measured with HIP events on the stream it runs
 on, against the nominal LDS bandwidth of the chip (128 B/clk/CU * 256 CUs *
 2.4 GHz).  The mark count is exact: for every base prime p > 61 the number of
-m coprime to 6 with max(p^2, tile base) <= m*p < tile-span end.
+m coprime to 30 with max(p^2, tile base) <= m*p < tile-span end.
 
 The CPU baseline is the oracle (plain byte-per-integer segmented sieve, all
 host threads) timed on a bounded slice of the same workload.
@@ -62,8 +62,21 @@ def coprime6_upto(n: np.ndarray) -> np.ndarray:
     return 2 * q + (s >= 1) + (s >= 5)
 
 
+_C30 = np.array([sum(1 for m in range(1, r + 1) if math.gcd(m, 30) == 1) for r in range(30)])
+
+
+def coprime30_upto(n: np.ndarray) -> np.ndarray:
+    """#{1 <= m <= n : gcd(m, 30) = 1}, elementwise, n >= 0."""
+    q, s = np.divmod(n, 30)
+    return 8 * q + _C30[s]
+
+
 def lds_work(lo: int, hi: int, segment_bytes: int) -> tuple[int, int]:
-    """(marks, plane words) the sieve kernel performs on [lo, hi)."""
+    """(marks, plane words) the sieve kernel performs on [lo, hi).
+
+    Primes 5..61 are presieved; every other base prime p marks p*m for the
+    cofactors m coprime to 30 (multiples of 2, 3 are outside the wheel and
+    multiples of 5 are already cleared by the presieve)."""
     pw = segment_bytes // 8
     base = lo - lo % 6
     n1 = (hi - base - 1 + 5) // 6
@@ -80,7 +93,7 @@ def lds_work(lo: int, hi: int, segment_bytes: int) -> tuple[int, int]:
     m_lo = -(-start // p)
     m_hi = (end - 1) // p
     ok = m_hi >= m_lo
-    marks = int(np.sum(np.where(ok, coprime6_upto(m_hi) - coprime6_upto(m_lo - 1), 0)))
+    marks = int(np.sum(np.where(ok, coprime30_upto(m_hi) - coprime30_upto(m_lo - 1), 0)))
     del ntiles, tile_span
     return marks, int(words)
 

@@ -79,6 +79,17 @@ typedef struct sieve_ctx sieve_ctx;
  *                    SIEVE_BUCKET_NEVER disables the bucket sieve.
  *   wg_per_cu        persistent workgroups launched per compute unit.
  *   use_graph        1: batched calls replay a captured hipGraph.
+ *   bucket_slices    bucket storage layout: 0 (default) sizes each tile's
+ *                    slice from the expected hit count plus a wide margin
+ *                    and re-runs a job exactly when a slice overflows;
+ *                    SIEVE_BUCKET_EXACT always counts first (two passes);
+ *                    SIEVE_BUCKET_TINY gives every slice one entry, which
+ *                    exercises the overflow re-run (tests).
+ *   cofactor_skip    where marks whose cofactor is a multiple of 5 are
+ *                    skipped (such values are already cleared by the 5 of the
+ *                    presieve): 0 (default) in the bucket sieve only;
+ *                    SIEVE_SKIP_ALL also in the per-tile marking loop;
+ *                    SIEVE_SKIP_NONE nowhere.  Needs presieve_groups >= 1.
  */
 typedef struct sieve_params {
     uint32_t segment_bytes;
@@ -88,11 +99,17 @@ typedef struct sieve_params {
     uint32_t bucket_threshold;
     uint32_t wg_per_cu;
     uint32_t use_graph;
+    uint32_t bucket_slices;
+    uint32_t cofactor_skip;
     uint32_t reserved;
 } sieve_params;
 
 #define SIEVE_PRESIEVE_NONE 0xFFFFFFFFu
 #define SIEVE_BUCKET_NEVER 0xFFFFFFFFu
+#define SIEVE_BUCKET_EXACT 1u
+#define SIEVE_BUCKET_TINY 2u
+#define SIEVE_SKIP_ALL 1u
+#define SIEVE_SKIP_NONE 2u
 
 /* Fills *p with the library defaults for gfx950. */
 int sieve_default_params(sieve_params *p);

@@ -37,6 +37,10 @@ SIEVE_E_BUSY = -7
 SIEVE_E_CANCELLED = -8
 PRESIEVE_NONE = 0xFFFFFFFF
 BUCKET_NEVER = 0xFFFFFFFF
+BUCKET_EXACT = 1
+BUCKET_TINY = 2
+SKIP_ALL = 1
+SKIP_NONE = 2
 
 _u64 = ctypes.c_uint64
 _p = ctypes.c_void_p
@@ -47,7 +51,8 @@ class Params(ctypes.Structure):
     _fields_ = [("segment_bytes", ctypes.c_uint32), ("block_threads", ctypes.c_uint32),
                 ("presieve_groups", ctypes.c_uint32), ("split_hits", ctypes.c_uint32),
                 ("bucket_threshold", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32),
-                ("use_graph", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("use_graph", ctypes.c_uint32), ("bucket_slices", ctypes.c_uint32),
+                ("cofactor_skip", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

@@ -119,6 +119,8 @@ int validate_params(const sieve_params &p, uint32_t lds_max)
         return SIEVE_E_INVAL;
     if (p.wg_per_cu < 1 || p.wg_per_cu > 16)
         return SIEVE_E_INVAL;
+    if (p.bucket_slices > SIEVE_BUCKET_TINY || p.cofactor_skip > SIEVE_SKIP_NONE)
+        return SIEVE_E_INVAL;
     return SIEVE_OK;
 }
 
@@ -179,10 +181,8 @@ int install_primes(sieve_ctx *c, uint64_t limit)
     const std::vector<uint32_t> &P = c->h_primes;
     const size_t n = P.size();
     std::vector<PrimeConst> prm(std::max<size_t>(n, 1), PrimeConst{0, 0, 0, 0});
-    for (size_t k = 0; k < n; ++k) {
-        const uint64_t m = UINT64_MAX / P[k];
-        prm[k] = PrimeConst{P[k], P[k] / 6, (uint32_t)m, (uint32_t)(m >> 32)};
-    }
+    for (size_t k = 0; k < n; ++k)
+        prm[k] = make_prime_const(P[k]);
     const size_t np = limit / 64 + 2;
     std::vector<uint32_t> pidx(np);
     size_t k = 0;
@@ -210,6 +210,8 @@ int install_primes(sieve_ctx *c, uint64_t limit)
         if (g <= 1)
             break;
         g = std::min<uint64_t>(g, 0xFFFF);
+        if (g % 5 == 0)
+            --g;  // a lane's cofactors then run through every residue mod 5
         for (uint32_t j = 0; j < g; ++j)
             items.push_back(make_uint2(ks, (j << 16) | (uint32_t)g));
         prefix.push_back((uint32_t)items.size());
@@ -230,6 +232,9 @@ int install_primes(sieve_ctx *c, uint64_t limit)
         e = hipMemcpy(c->d_item_prefix.p, prefix.data(), prefix.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e != hipSuccess)
         return hip_status(e);
+    c->inv_prefix.assign(n + 1, 0.0);
+    for (size_t j = 0; j < n; ++j)
+        c->inv_prefix[j + 1] = c->inv_prefix[j] + 1.0 / P[j];
     // Bucket sieve: primes at least the threshold (default four plane lengths,
     // where a prime hits a given tile with probability below 1/2).
     const uint64_t thr = c->prm.bucket_threshold ? (uint64_t)c->prm.bucket_threshold : 4 * plane_bits;
@@ -265,6 +270,7 @@ struct Plan {
     std::vector<uint32_t> list_idx;
     std::vector<uint64_t> list_chunk0;
     uint64_t ntiles = 0, nchunks = 0, nunits = 0;
+    uint64_t best = 0;  // bucket entries of the estimated layout
 };
 
 int make_plan(const sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, const uint8_t *mode,
@@ -308,6 +314,18 @@ int make_plan(const sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t
         d.bunits = d.kbig < d.nact ? ((d.nact - d.kbig + kBucketThreads - 1) / kBucketThreads) * d.bwins : 0;
         d.bunit0 = pl.nunits;
         pl.nunits += d.bunits;
+        if (d.bunits) {
+            // Expected entries per tile: each large prime p hits a plane of
+            // nbits bits nbits/p times on average; reserve that plus a
+            // margin of 8 standard deviations (the count is a sum of nearly
+            // independent rare events) and 64.
+            const double nbits = 32.0 * pw;
+            const double E = 2.0 * nbits * (c->inv_prefix[d.nact] - c->inv_prefix[d.kbig]);
+            const double capd = E + 8.0 * std::sqrt(E) + 64.0;
+            d.bcap = c->prm.bucket_slices == SIEVE_BUCKET_TINY ? 1u : (uint32_t)std::min(capd, 4.0e9);
+            d.bbase = pl.best;
+            pl.best += (uint64_t)d.bcap * nt;
+        }
         d.mode = lst ? 1u : 0u;
         if (lst) {
             d.out_off = off ? off[i] : 0;
@@ -413,7 +431,7 @@ int ensure_capacity(sieve_ctx *c, uint64_t nranges, uint64_t nlist, uint64_t nch
     if (!c->d_counters.p) {
         if (!c->d_counters.reserve(kNumCounters))
             return SIEVE_E_NOMEM;
-        if (hipHostMalloc((void **)&c->h_flag, sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
+        if (hipHostMalloc((void **)&c->h_flag, 2 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc((void **)&c->h_btotal, sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
             return SIEVE_E_NOMEM;
@@ -425,14 +443,15 @@ int ensure_capacity(sieve_ctx *c, uint64_t nranges, uint64_t nlist, uint64_t nch
     return SIEVE_OK;
 }
 
-enum Phase { kPhaseWhole = 0, kPhaseBucketCount = 1, kPhaseRest = 2 };
+enum Phase { kPhaseWhole = 0, kPhaseBucketCount = 1, kPhaseRest = 2, kPhaseDirect = 3 };
 
 // Enqueues one phase of the job kernels on stream s; also used under graph
 // capture.  All job-specific values are read by the kernels from the device
 // blob, whose layout depends only on the capacities.
 //   whole:         zero, sieve, finalize, compact       (jobs without buckets)
-//   bucket count:  zero, bucket count, bucket scan
-//   rest:          bucket fill, sieve, finalize, compact
+//   direct:        zero, estimated bucket fill, sieve, finalize, compact
+//   bucket count:  zero, exact bucket count, bucket scan
+//   rest:          exact bucket fill, sieve, finalize, compact
 hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed)
 {
     const BlobLayout L = blob_layout(c->cap_ranges, c->cap_list);
@@ -449,6 +468,8 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed)
     b.bcursor = c->d_bcursor.p;
     b.boff = c->d_boff.p;
     b.bdata = c->d_bdata.p;
+    b.counters = c->d_counters.p;
+    b.skip5 = (c->ngroups >= 1 && c->prm.cofactor_skip != SIEVE_SKIP_NONE) ? 1u : 0u;
     b.nbits = 32 * pw;
     b.span = 192ull * pw;
     b.span_rcp = UINT64_MAX / b.span;
@@ -456,7 +477,9 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed)
     if (phase != kPhaseRest) {
         if (timed && phase == kPhaseBucketCount && (e = hipEventRecord(c->ev[3], s)) != hipSuccess)
             return e;
-        if ((e = launch_zero(job, c->d_counters.p, c->d_counts.p, c->d_bcount.p, s)) != hipSuccess)
+        // per-tile counts (exact layout) or cursors (estimated layout) start at 0
+        uint32_t *bzero = phase == kPhaseDirect ? c->d_bcursor.p : c->d_bcount.p;
+        if ((e = launch_zero(job, c->d_counters.p, c->d_counts.p, bzero, s)) != hipSuccess)
             return e;
     }
     if (phase == kPhaseBucketCount) {
@@ -473,10 +496,10 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed)
             return e;
         return hipSuccess;
     }
-    if (phase == kPhaseRest) {
+    if (phase == kPhaseRest || phase == kPhaseDirect) {
         if (timed && (e = hipEventRecord(c->ev[5], s)) != hipSuccess)
             return e;
-        if ((e = launch_bucket(b, 1, bgrid, s)) != hipSuccess)
+        if ((e = launch_bucket(b, phase == kPhaseRest ? 1 : 2, bgrid, s)) != hipSuccess)
             return e;
     }
     SieveArgs a;
@@ -500,11 +523,13 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed)
     a.restore1 = c->restore1;
     a.restore5 = c->restore5;
     a.pw = pw;
+    a.skip5 = (c->ngroups >= 1 && c->prm.cofactor_skip == SIEVE_SKIP_ALL) ? 1u : 0u;
     a.bitmap = c->d_bitmap.p;
     a.chunk_counts = c->d_chunk_counts.p;
     a.bdata = c->d_bdata.p;
     a.boff = c->d_boff.p;
     a.bcount = c->d_bcount.p;
+    a.bcursor = c->d_bcursor.p;
     if (timed && (e = hipEventRecord(c->ev[0], s)) != hipSuccess)
         return e;
     e = launch_sieve(a, c->prm.block_threads, (uint32_t)c->cus * c->prm.wg_per_cu, s);
@@ -601,6 +626,7 @@ int run_job(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, co
     h->ntiles = pl.ntiles;
     h->nchunks = pl.nchunks;
     h->nunits = pl.nunits;
+    h->bmode = 1;
     h->nranges = (uint32_t)n;
     h->nlist = (uint32_t)nlist;
     h->out = out;
@@ -619,56 +645,84 @@ int run_job(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, co
     if (e != hipSuccess)
         return hip_status(e);
     const bool buckets = pl.nunits != 0;
-    if (buckets) {
-        // Count the bucket entries, then size the entry store exactly.
-        if ((e = run_phase(c, s, kPhaseBucketCount, use_graph)) != hipSuccess)
-            return hip_status(e);
-        e = hipMemcpyAsync(c->h_btotal, c->d_boff.p + pl.ntiles, sizeof(unsigned long long),
-                           hipMemcpyDeviceToHost, s);
+    // Results back to the host: per-range counts and status, and the flags.
+    auto finish = [&]() -> hipError_t {
+        hipError_t f = hipSuccess;
+        if (n) {
+            f = hipMemcpyAsync(c->h_counts, c->d_counts.p, n * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                               s);
+            if (f == hipSuccess)
+                f = hipMemcpyAsync(c->h_status, c->d_status.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        }
+        if (f == hipSuccess)
+            f = hipMemcpyAsync(c->h_flag, c->d_counters.p + kErrorFlag, 2 * sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, s);
+        if (f == hipSuccess)
+            f = hipStreamSynchronize(s);
+        return f;
+    };
+    if (!buckets) {
+        e = run_phase(c, s, kPhaseWhole, use_graph);
         if (e == hipSuccess)
-            e = hipStreamSynchronize(s);
-        if (e != hipSuccess)
-            return hip_status(e);
-        const uint64_t total = *c->h_btotal;
-        if (total > c->cap_bdata) {
-            c->cap_bdata = grow(c->cap_bdata, total, 1024);
+            e = finish();
+    } else {
+        // Estimated layout first: one pass, no host round trip.
+        if (c->prm.bucket_slices == SIEVE_BUCKET_EXACT)
+            pl.best = 0;
+        if (pl.best > c->cap_bdata) {
+            c->cap_bdata = grow(c->cap_bdata, pl.best, 1024);
             c->d_bdata.release();
             if (!c->d_bdata.reserve(c->cap_bdata))
                 return SIEVE_E_NOMEM;
             c->gen++;
         }
-        e = run_phase(c, s, kPhaseRest, use_graph);
-    } else {
-        e = run_phase(c, s, kPhaseWhole, use_graph);
+        const bool exact = c->prm.bucket_slices == SIEVE_BUCKET_EXACT;
+        if (!exact) {
+            e = run_phase(c, s, kPhaseDirect, use_graph);
+            if (e == hipSuccess)
+                e = finish();
+        }
+        if (e == hipSuccess && (exact || c->h_flag[1])) {
+            // A slice overflowed: run the job again with the exact layout.
+            c->bucket_fallbacks++;
+            h->bmode = 2;
+            e = hipMemcpyAsync(c->d_blob.p, c->h_blob, sizeof(JobHeader), hipMemcpyHostToDevice, s);
+            if (e == hipSuccess)
+                e = run_phase(c, s, kPhaseBucketCount, use_graph);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(c->h_btotal, c->d_boff.p + pl.ntiles, sizeof(unsigned long long),
+                                   hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess)
+                e = hipStreamSynchronize(s);
+            if (e == hipSuccess && *c->h_btotal > c->cap_bdata) {
+                c->cap_bdata = grow(c->cap_bdata, *c->h_btotal, 1024);
+                c->d_bdata.release();
+                if (!c->d_bdata.reserve(c->cap_bdata))
+                    return SIEVE_E_NOMEM;
+                c->gen++;
+            }
+            if (e == hipSuccess)
+                e = run_phase(c, s, kPhaseRest, use_graph);
+            if (e == hipSuccess)
+                e = finish();
+        }
     }
     if (e != hipSuccess)
         return hip_status(e);
-    if (n) {
-        e = hipMemcpyAsync(c->h_counts, c->d_counts.p, n * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(c->h_status, c->d_status.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s);
-        if (e != hipSuccess)
-            return hip_status(e);
-    }
-    e = hipMemcpyAsync(c->h_flag, c->d_counters.p + kErrorFlag, sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                       s);
-    if (e != hipSuccess)
-        return hip_status(e);
-    if ((e = hipStreamSynchronize(s)) != hipSuccess)
-        return hip_status(e);
-    if (*c->h_flag)
+    if (c->h_flag[0])
         return SIEVE_E_DEVICE;  // a kernel refused to run (see its error flag)
     if (c->timing && !use_graph) {
-        float a = 0, b = 0, bc = 0, bf = 0;
-        if (hipEventElapsedTime(&a, c->ev[0], c->ev[1]) == hipSuccess &&
-            hipEventElapsedTime(&b, c->ev[1], c->ev[2]) == hipSuccess) {
-            c->t_sieve_ms += a;
-            c->t_post_ms += b;
+        float ta = 0, tb = 0, bc = 0, bf = 0;
+        if (hipEventElapsedTime(&ta, c->ev[0], c->ev[1]) == hipSuccess &&
+            hipEventElapsedTime(&tb, c->ev[1], c->ev[2]) == hipSuccess) {
+            c->t_sieve_ms += ta;
+            c->t_post_ms += tb;
             c->t_jobs++;
         }
-        if (buckets && hipEventElapsedTime(&bc, c->ev[3], c->ev[4]) == hipSuccess &&
-            hipEventElapsedTime(&bf, c->ev[5], c->ev[0]) == hipSuccess)
-            c->t_bucket_ms += bc + bf;
+        if (buckets && hipEventElapsedTime(&bf, c->ev[5], c->ev[0]) == hipSuccess)
+            c->t_bucket_ms += bf;
+        if (buckets && h->bmode == 2 && hipEventElapsedTime(&bc, c->ev[3], c->ev[4]) == hipSuccess)
+            c->t_bucket_ms += bc;
     }
     for (uint64_t i = 0; i < n; ++i) {
         if (counts)
@@ -722,7 +776,7 @@ void destroy_ctx(sieve_ctx *c)
 {
     if (!c)
         return;
-    for (int g = 0; g < 3; ++g) {
+    for (int g = 0; g < 4; ++g) {
         if (c->graph[g])
             (void)hipGraphExecDestroy(c->graph[g]);
         if (c->graph_src[g])

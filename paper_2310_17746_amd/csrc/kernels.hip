@@ -101,6 +101,50 @@ __device__ __forceinline__ void mark_plane(uint32_t base, uint64_t start, uint32
         lds_or(((i >> 3) & ~3u) + base, 1u << (i & 31));
 }
 
+// As mark_plane, for a lane whose hits n = 0, 1, 2, ... have cofactors
+// running through the residues mod 5 with period 5, skipping hit n when
+// n = s (mod 5): those values are multiples of 5, already cleared by the
+// presieve, so a fifth of the LDS operations is saved.  s in 0..4.
+__device__ __forceinline__ void mark_plane_skip5(uint32_t base, uint64_t start, uint32_t step, uint32_t nbits,
+                                                 uint32_t s)
+{
+    if (start >= nbits)
+        return;
+    uint32_t i = (uint32_t)start;
+    if (step < nbits / 5) {
+        // kept offsets of one period of five hits
+        const uint32_t s2 = step + step, s3 = s2 + step, s4 = s3 + step;
+        const uint32_t o0 = s == 0 ? step : 0u;
+        const uint32_t o1 = s <= 1 ? s2 : step;
+        const uint32_t o2 = s <= 2 ? s3 : s2;
+        const uint32_t o3 = s <= 3 ? s4 : s3;
+        const uint32_t lim = nbits - 4 * step;  // i < lim keeps i + 4*step < nbits
+        while (i < lim) {
+            asm volatile("" : "+v"(i));
+            const uint32_t i0 = i + o0, i1 = i + o1, i2 = i + o2, i3 = i + o3;
+            lds_or(((i0 >> 3) & ~3u) + base, 1u << (i0 & 31));
+            lds_or(((i1 >> 3) & ~3u) + base, 1u << (i1 & 31));
+            lds_or(((i2 >> 3) & ~3u) + base, 1u << (i2 & 31));
+            lds_or(((i3 >> 3) & ~3u) + base, 1u << (i3 & 31));
+            i += 5 * step;
+        }
+    }
+    for (uint32_t n = 0; n < 5; ++n) {
+        const uint64_t x = (uint64_t)i + (uint64_t)n * step;
+        if (x >= nbits)
+            break;
+        if (n != s)
+            lds_or((((uint32_t)x >> 3) & ~3u) + base, 1u << ((uint32_t)x & 31));
+    }
+}
+
+// Residue mod 5 of the cofactor m of the value B + 6*id + r = m * P, from
+// B mod 5 and P^-1 mod 5 (6 = 1 mod 5).
+__device__ __forceinline__ uint32_t cofactor_mod5(uint32_t b5, uint32_t id, uint32_t r, uint32_t inv5)
+{
+    return ((b5 + id % 5u + r) * inv5) % 5u;
+}
+
 }  // namespace
 
 // Bookkeeping of one tile, kept in LDS after the two planes so that the
@@ -223,6 +267,7 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
             const uint32_t n_work = n_items + n_rest;
             // Every active prime is below 2^31 when the tile ends below 2^62.
             const bool narrow = tend <= (1ull << 62);
+            const uint32_t b5 = (uint32_t)(B % 5);
             for (uint32_t v = tid; v < n_work; v += NT) {
                 uint32_t kp, j, g;
                 if (v < n_items) {
@@ -241,15 +286,30 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
                 if (M >= tend)
                     continue;
                 uint32_t id1, id5;
-                wheel_start(pc.p, pc.r, ((uint64_t)pc.m_hi << 32) | pc.m_lo, B, M, narrow, id1, id5);
+                const uint32_t R = pc.r & 0x1FFFFFFFu, inv5 = pc.r >> 29;
+                wheel_start(pc.p, R, ((uint64_t)pc.m_hi << 32) | pc.m_lo, B, M, narrow, id1, id5);
                 const uint32_t step = g * pc.p;
                 const uint32_t off = j * pc.p;
-                mark_plane(0, (uint64_t)id1 + off, step, nbits);
-                mark_plane(base5, (uint64_t)id5 + off, step, nbits);
+                if (a.skip5) {
+                    // hit n of this lane has cofactor m0 + 6(j + n g) = c + n g (mod 5);
+                    // it is a multiple of 5 when n = -c / g (mod 5)
+                    const uint32_t ginv = inv_mod5(g);
+                    const uint32_t c1 = (cofactor_mod5(b5, id1, 1, inv5) + j) % 5u;
+                    const uint32_t c5 = (cofactor_mod5(b5, id5, 0, inv5) + j) % 5u;
+                    mark_plane_skip5(0, (uint64_t)id1 + off, step, nbits, ((5u - c1) * ginv) % 5u);
+                    mark_plane_skip5(base5, (uint64_t)id5 + off, step, nbits, ((5u - c5) * ginv) % 5u);
+                } else {
+                    mark_plane(0, (uint64_t)id1 + off, step, nbits);
+                    mark_plane(base5, (uint64_t)id5 + off, step, nbits);
+                }
             }
             // Bucket entries of this tile: one mark each.
             if (d.kbig < d.nact) {
-                const uint64_t e0 = a.boff[t], ne = a.bcount[t];
+                const bool est = a.job->bmode == 1;
+                const uint64_t e0 = est ? d.bbase + k * d.bcap : a.boff[t];
+                uint64_t ne = est ? a.bcursor[t] : a.bcount[t];
+                if (est && ne > d.bcap)
+                    ne = d.bcap;  // overflowed slice: the job is run again exactly
                 for (uint64_t e = tid; e < ne; e += NT) {
                     const uint32_t v = a.bdata[e0 + e];
                     const uint32_t bit = v & 0x7FFFFFFFu;
@@ -339,18 +399,26 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
 // start per (tile, prime) it gets one start per range and its hits are
 // walked tile by tile: each hit advances by (P div nbits) tiles and
 // (P mod nbits) bits.  Hits are binned per tile in LDS windows of
-// kBucketWindow tiles.  The count pass adds the per-tile totals; after a
-// scan, the fill pass reserves each tile's slice with one global atomic per
-// (workgroup, tile) and writes the entries (bit | plane << 31).
+// kBucketWindow tiles.  Two layouts:
+//  - estimated (PASS 2): every tile of a range has a slice sized from the
+//    expected hit count plus a wide margin; the fill pass reserves with one
+//    global atomic per (workgroup, tile) and flags a slice that would
+//    overflow (the job is then run again with the exact layout);
+//  - exact: the count pass (PASS 0) adds the per-tile totals, a scan gives
+//    offsets, and the fill pass (PASS 1) writes into them.
+// Entries are bit | plane << 31.
 // ---------------------------------------------------------------------------
 namespace {
 
 struct HitWalk {
     uint32_t t1, b1, t5, b5;  // next hit (tile, bit) per plane; t = ntiles when done
     uint32_t qp, rp;          // P div nbits, P mod nbits
+    uint32_t c1, c5;          // residue mod 5 of the next hit's cofactor (5: not tracked)
 };
 
-__device__ inline void walk_step(uint32_t &t, uint32_t &b, const HitWalk &w, uint32_t nbits)
+// Next hit of one plane: P indices further, i.e. 6P in value, so the
+// cofactor grows by 6 = 1 (mod 5).
+__device__ inline void walk_step(uint32_t &t, uint32_t &b, uint32_t &c, const HitWalk &w, uint32_t nbits)
 {
     b += w.rp;
     t += w.qp;
@@ -358,6 +426,7 @@ __device__ inline void walk_step(uint32_t &t, uint32_t &b, const HitWalk &w, uin
         b -= nbits;
         t += 1;
     }
+    c = c == 4 ? 0 : (c == 5 ? 5 : c + 1);
 }
 
 // First hits of prime k in tiles [w0, wend) of range d (tile indices
@@ -369,6 +438,7 @@ __device__ inline HitWalk walk_init(const BucketArgs &a, const RangeDesc &d, uin
     w.t1 = w.t5 = wend;
     w.b1 = w.b5 = 0;
     w.qp = w.rp = 0;
+    w.c1 = w.c5 = 5;
     if (k >= d.nact)
         return w;
     const PrimeConst pc = a.prm[k];
@@ -386,7 +456,13 @@ __device__ inline HitWalk walk_init(const BucketArgs &a, const RangeDesc &d, uin
         ++tM;
     const uint64_t Bt = d.base + tM * a.span;
     uint32_t id1, id5;
-    wheel_start(pc.p, pc.r, ((uint64_t)pc.m_hi << 32) | pc.m_lo, Bt, M, rend <= (1ull << 62), id1, id5);
+    const uint32_t R = pc.r & 0x1FFFFFFFu, inv5 = pc.r >> 29;
+    wheel_start(pc.p, R, ((uint64_t)pc.m_hi << 32) | pc.m_lo, Bt, M, rend <= (1ull << 62), id1, id5);
+    if (a.skip5) {
+        const uint32_t bt5 = (uint32_t)(Bt % 5);
+        w.c1 = cofactor_mod5(bt5, id1, 1, inv5);
+        w.c5 = cofactor_mod5(bt5, id5, 0, inv5);
+    }
     w.qp = pc.p / a.nbits;
     w.rp = pc.p - w.qp * a.nbits;
     const uint64_t t1 = tM + id1 / a.nbits, t5 = tM + id5 / a.nbits;
@@ -441,12 +517,14 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket(BucketArgs a)
         __syncthreads();
         if (PASS == 0) {
             while (w.t1 < wend) {
-                atomicAdd(&s_cnt[w.t1 - w0], 1u);
-                walk_step(w.t1, w.b1, w, nbits);
+                if (w.c1)
+                    atomicAdd(&s_cnt[w.t1 - w0], 1u);
+                walk_step(w.t1, w.b1, w.c1, w, nbits);
             }
             while (w.t5 < wend) {
-                atomicAdd(&s_cnt[w.t5 - w0], 1u);
-                walk_step(w.t5, w.b5, w, nbits);
+                if (w.c5)
+                    atomicAdd(&s_cnt[w.t5 - w0], 1u);
+                walk_step(w.t5, w.b5, w.c5, w, nbits);
             }
             __syncthreads();
             for (uint32_t i = tid; i < wend - w0; i += kBucketThreads)
@@ -456,12 +534,14 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket(BucketArgs a)
             {
                 HitWalk c = w;  // count first, without moving the walk
                 while (c.t1 < wend) {
-                    atomicAdd(&s_cnt[c.t1 - w0], 1u);
-                    walk_step(c.t1, c.b1, c, nbits);
+                    if (c.c1)
+                        atomicAdd(&s_cnt[c.t1 - w0], 1u);
+                    walk_step(c.t1, c.b1, c.c1, c, nbits);
                 }
                 while (c.t5 < wend) {
-                    atomicAdd(&s_cnt[c.t5 - w0], 1u);
-                    walk_step(c.t5, c.b5, c, nbits);
+                    if (c.c5)
+                        atomicAdd(&s_cnt[c.t5 - w0], 1u);
+                    walk_step(c.t5, c.b5, c.c5, c, nbits);
                 }
             }
             __syncthreads();
@@ -469,19 +549,35 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket(BucketArgs a)
                 const uint32_t n = s_cnt[i];
                 if (n) {
                     const uint64_t g = d.tile0 + w0 + i;
-                    s_base[i] = a.boff[g] + atomicAdd(&a.bcursor[g], n);
+                    const uint32_t at = atomicAdd(&a.bcursor[g], n);
+                    if (PASS == 1) {
+                        s_base[i] = a.boff[g] + at;
+                    } else if (at + n <= d.bcap) {
+                        s_base[i] = d.bbase + (uint64_t)(w0 + i) * d.bcap + at;
+                    } else {
+                        s_base[i] = ~0ull;  // slice full: flag it, write nothing
+                        atomicOr(&a.counters[kOverflowFlag], 1ull);
+                    }
                 }
             }
             __syncthreads();
             while (w.t1 < wend) {
-                const uint32_t slot = atomicAdd(&s_cur[w.t1 - w0], 1u);
-                a.bdata[s_base[w.t1 - w0] + slot] = w.b1;
-                walk_step(w.t1, w.b1, w, nbits);
+                if (w.c1) {
+                    const uint32_t slot = atomicAdd(&s_cur[w.t1 - w0], 1u);
+                    const unsigned long long b0 = s_base[w.t1 - w0];
+                    if (b0 != ~0ull)
+                        a.bdata[b0 + slot] = w.b1;
+                }
+                walk_step(w.t1, w.b1, w.c1, w, nbits);
             }
             while (w.t5 < wend) {
-                const uint32_t slot = atomicAdd(&s_cur[w.t5 - w0], 1u);
-                a.bdata[s_base[w.t5 - w0] + slot] = w.b5 | 0x80000000u;
-                walk_step(w.t5, w.b5, w, nbits);
+                if (w.c5) {
+                    const uint32_t slot = atomicAdd(&s_cur[w.t5 - w0], 1u);
+                    const unsigned long long b0 = s_base[w.t5 - w0];
+                    if (b0 != ~0ull)
+                        a.bdata[b0 + slot] = w.b5 | 0x80000000u;
+                }
+                walk_step(w.t5, w.b5, w.c5, w, nbits);
             }
         }
         __syncthreads();
@@ -677,7 +773,7 @@ __global__ void k_zero(const JobHeader *job, unsigned long long *counters, unsig
         counts[i] = 0;
     if (job->nunits)
         for (uint64_t i = g; i < job->ntiles; i += gridDim.x * blockDim.x)
-            bcount[i] = 0;
+            bcount[i] = 0;  // count (exact layout) or cursor (estimated layout)
 }
 
 // ---------------------------------------------------------------------------
@@ -707,8 +803,10 @@ hipError_t launch_bucket(const BucketArgs &a, int pass, uint32_t grid, hipStream
 {
     if (pass == 0)
         hipLaunchKernelGGL(k_bucket<0>, dim3(grid), dim3(kBucketThreads), 0, s, a);
-    else
+    else if (pass == 1)
         hipLaunchKernelGGL(k_bucket<1>, dim3(grid), dim3(kBucketThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_bucket<2>, dim3(grid), dim3(kBucketThreads), 0, s, a);
     return hipGetLastError();
 }
 

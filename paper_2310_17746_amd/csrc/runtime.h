@@ -71,6 +71,8 @@ struct sieve_ctx {
     sieve::rt::DevBuf<uint32_t> d_item_prefix;
     uint32_t first_mark = 0, k_split = 0;
     uint32_t k_large = 0;  // first prime index the bucket sieve takes (multi-tile ranges)
+    std::vector<double> inv_prefix;  // inv_prefix[k] = sum of 1/p over the first k primes
+    uint64_t bucket_fallbacks = 0;   // jobs re-run with the exact bucket layout
 
     // Presieve tables.
     sieve::rt::DevBuf<uint2> d_pstab;
@@ -90,7 +92,7 @@ struct sieve_ctx {
     size_t h_blob_n = 0;
     unsigned long long *h_counts = nullptr;  // pinned
     int32_t *h_status = nullptr;             // pinned
-    unsigned long long *h_flag = nullptr;    // pinned copy of the kernels' error flag
+    unsigned long long *h_flag = nullptr;    // pinned copy of the error and overflow flags
     uint64_t cap_ranges = 0, cap_list = 0, cap_chunks = 0;
 
     // Bucket sieve scratch: per-tile counts, cursors and offsets; entries.
@@ -99,12 +101,13 @@ struct sieve_ctx {
     unsigned long long *h_btotal = nullptr;  // pinned
     uint64_t cap_tiles = 0, cap_bdata = 0;
 
-    // Graphs of the job phases (0: whole job without buckets, 1: bucket
-    // count + scan, 2: bucket fill + sieve + finalize + compact); each is
-    // valid while gen == graph_gen[i].
-    hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
-    hipGraph_t graph_src[3] = {nullptr, nullptr, nullptr};
-    uint64_t graph_gen[3] = {~0ull, ~0ull, ~0ull};
+    // Graphs of the job phases (0: whole job without buckets, 1: exact
+    // bucket count + scan, 2: exact bucket fill + sieve + finalize + compact,
+    // 3: estimated bucket fill + sieve + finalize + compact); each is valid
+    // while gen == graph_gen[i].
+    hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipGraph_t graph_src[4] = {nullptr, nullptr, nullptr, nullptr};
+    uint64_t graph_gen[4] = {~0ull, ~0ull, ~0ull, ~0ull};
     uint64_t gen = 0;
 
     // Optional event timing of the sieve kernel and the post-processing.

@@ -50,6 +50,9 @@ struct RangeDesc {
     uint64_t bunit0;     // first bucket work unit of this range
     uint32_t bunits;     // bucket work units: prime blocks x tile windows
     uint32_t bwins;      // tile windows of kBucketWindow tiles
+    uint64_t bbase;      // estimated layout: first entry of this range's buckets
+    uint32_t bcap;       // estimated layout: entries reserved per tile
+    uint32_t pad;
 };
 
 // Per-job scalars, in device memory so that a captured graph can be replayed
@@ -58,6 +61,8 @@ struct JobHeader {
     uint64_t ntiles;     // tiles over all ranges
     uint64_t nchunks;    // bitmap chunks over all list ranges
     uint64_t nunits;     // bucket work units over all ranges
+    uint32_t bmode;      // bucket layout: 1 estimated per-range slices, 2 exact per-tile offsets
+    uint32_t pad0;
     uint32_t nranges;
     uint32_t nlist;      // list ranges
     void *out;           // caller's output buffer (list ranges)
@@ -66,7 +71,7 @@ struct JobHeader {
 };
 
 // Counters zeroed at the start of every job.
-enum Counter { kTileCounter = 0, kChunkCounter = 1, kErrorFlag = 2, kNumCounters = 4 };
+enum Counter { kTileCounter = 0, kChunkCounter = 1, kErrorFlag = 2, kOverflowFlag = 3, kNumCounters = 4 };
 
 // A presieve pattern group: primes whose product is `period`.  Its table
 // holds period + 64 bits per plane (bit t stands for 6t + r, set when some
@@ -99,11 +104,13 @@ struct SieveArgs {
     uint32_t ngroups;
     uint32_t restore1, restore5;  // bits of the presieved primes in word 0 of a tile based at 0
     uint32_t pw;                  // plane words per tile
+    uint32_t skip5;               // 1: multiples of 5 are presieved, so no mark with 5 | cofactor
     unsigned long long *bitmap;   // list scratch (u64 words)
     uint32_t *chunk_counts;       // per chunk prime count
     const uint32_t *bdata;        // bucket entries: bit | plane << 31
-    const unsigned long long *boff;  // per tile: first entry
-    const uint32_t *bcount;       // per tile: entries
+    const unsigned long long *boff;  // exact layout, per tile: first entry
+    const uint32_t *bcount;       // exact layout, per tile: entries
+    const uint32_t *bcursor;      // estimated layout, per tile: entries written
 };
 
 // Bucket sieve (large primes of multi-tile ranges).  One work unit is a block
@@ -117,6 +124,8 @@ struct BucketArgs {
     uint32_t *bcursor;            // per tile (fill pass: reserved so far)
     const unsigned long long *boff;
     uint32_t *bdata;
+    unsigned long long *counters; // kOverflowFlag set when an estimated slice overflows
+    uint32_t skip5;               // as in SieveArgs
     uint32_t nbits;               // bits per plane per tile (32 * pw)
     uint64_t span;                // integers per tile (192 * pw)
     uint64_t span_rcp;            // floor((2^64 - 1) / span)

@@ -55,10 +55,22 @@ constexpr uint64_t kTable1_id5_p5 = table1_row(kT5p5);
 // Per-prime constants resident on the device (16 bytes, one load).
 struct PrimeConst {
     uint32_t p;       // the prime, >= 5
-    uint32_t r;       // floor(p / 6)
+    uint32_t r;       // bits 0..28: floor(p / 6); bits 29..31: p^-1 mod 5 (0 for p = 5)
     uint32_t m_lo;    // floor((2^64 - 1) / p), low and high halves
     uint32_t m_hi;
 };
+
+// x^-1 mod 5 for x mod 5 in 1..4 (0 stays 0).
+__host__ __device__ inline uint32_t inv_mod5(uint32_t x)
+{
+    return (0x42310u >> (4u * (x % 5u))) & 0xFu;  // 0->0, 1->1, 2->3, 3->2, 4->4
+}
+
+__host__ __device__ inline PrimeConst make_prime_const(uint32_t p)
+{
+    const uint64_t m = UINT64_MAX / p;
+    return PrimeConst{p, (p / 6u) | (inv_mod5(p) << 29), (uint32_t)m, (uint32_t)(m >> 32)};
+}
 
 __host__ __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b)
 {

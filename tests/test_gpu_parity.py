@@ -196,6 +196,8 @@ def test_error_paths(sv):
     dict(segment_bytes=49152, block_threads=256, presieve_groups=3, split_hits=2048),
     dict(segment_bytes=16384, bucket_threshold=70000),          # most primes through buckets
     dict(segment_bytes=49152, bucket_threshold=pkg.BUCKET_NEVER),  # no bucket sieve
+    dict(cofactor_skip=pkg.SKIP_ALL, split_hits=24),            # skip 5 | cofactor in tiles too
+    dict(cofactor_skip=pkg.SKIP_NONE, bucket_threshold=70000, segment_bytes=16384),
 ])
 def test_parameter_grid_parity(params):
     with pkg.Sieve(0, params) as s:
@@ -216,8 +218,9 @@ def test_base_primes_match_oracle(sv):
         assert s.count(lo, hi) == oracle.count(lo, hi)
 
 
-@pytest.mark.parametrize("thr", [0, 200_000, pkg.BUCKET_NEVER])
-def test_bucket_sieve_long_ranges_at_1e15(thr):
+@pytest.mark.parametrize("thr,slices", [(0, 0), (200_000, 0), (pkg.BUCKET_NEVER, 0),
+                                        (0, pkg.BUCKET_EXACT), (0, pkg.BUCKET_TINY)])
+def test_bucket_sieve_long_ranges_at_1e15(thr, slices):
     """Multi-tile ranges near 10^15 with primes up to 3.2e7: bucketed and
     per-tile paths agree with the oracle and with each other."""
     rng = np.random.default_rng(21)
@@ -225,7 +228,7 @@ def test_bucket_sieve_long_ranges_at_1e15(thr):
     hi = lo + np.floor(10 ** rng.uniform(6, 7.7, 12)).astype(np.uint64)
     lo[0], hi[0] = 10 ** 15 - 3 * 10 ** 7, 10 ** 15  # many tiles, hi at the top
     mode = (np.arange(12) % 2).astype(np.uint8)
-    with pkg.Sieve(0, dict(bucket_threshold=thr)) as s:
+    with pkg.Sieve(0, dict(bucket_threshold=thr, bucket_slices=slices)) as s:
         s.ensure_base_for(int(hi.max()))
         cap = np.array([pkg.list_bound(int(a), int(b)) for a, b in zip(lo, hi)], dtype=np.uint64)
         off = np.concatenate([[0], np.cumsum(cap)[:-1]]).astype(np.uint64)
