@@ -24,7 +24,8 @@ host threads) timed on a bounded slice of the same workload.
   read.
 * batch_4096: the 4096 seeded uneven ranges (half listed as uint64) in one
   batched call replaying a captured graph, against the same ranges as one
-  plain call each; primes/s counts every prime counted or listed.
+  plain call each; primes/s counts every prime counted or listed.  Its launch
+  parameters come from the autotuner run on a 1024-range sample first.
 * serve_2000: 2000 seeded requests with Poisson arrivals at 0.8 x the
   saturated request rate (measured first with all requests at t = 0) and the
   count of [2, 10^12] submitted at t = 0; p50/p99 of completion - arrival.
@@ -98,6 +99,33 @@ def lds_work(lo: int, hi: int, segment_bytes: int) -> tuple[int, int]:
     return marks, int(words)
 
 
+KERNEL_SOURCES = ("paper_2310_17746_amd/csrc/kernels.hip", "paper_2310_17746_amd/csrc/wheel.h",
+                  "paper_2310_17746_amd/csrc/sieve_internal.h")
+
+
+def kernel_sources_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per k_sieve dispatch from the committed counter summary, if it
+    was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "k_sieve_pi1e11_traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sources_sha256") != kernel_sources_sha():
+        return None
+    return t
+
+
 def bench_list(pkg, torch, params, steps=5):
     """Config 2: sorted uint32 list of the primes in [2, 10^9]."""
     lo, hi = 2, 10 ** 9 + 1
@@ -162,6 +190,39 @@ def bench_batch(pkg, torch, params, workloads, steps=3):
             "primes_per_s": round(primes / dt, 1),
             "per_range_ms": round(dt_single * 1e3, 3),
             "batched_vs_per_range": round(dt_single / dt, 3)}
+
+
+def bench_stream(pkg, torch, params):
+    """Incremental generation and streaming to host memory."""
+    s = pkg.Sieve(0, params)
+    # Generator: 2^24 primes per call from 10^12 (device output, uint64).
+    g = s.generator(10 ** 12, 8)
+    out = torch.empty(1 << 24, dtype=torch.int64, device="cuda")
+    g.next(1 << 24, out=out)  # warm-up: base primes, staging buffer
+    torch.cuda.synchronize()
+    calls = 8
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        g.next(1 << 24, out=out)
+    torch.cuda.synchronize()
+    dt_gen = (time.perf_counter() - t0) / calls
+    pos = g.position
+    g.close()
+    # Host stream: the uint64 list of [10^12, 10^12 + 10^10) into pinned host memory.
+    lo, hi = 10 ** 12, 10 ** 12 + 10 ** 10
+    s.ensure_base_for(hi)
+    host = torch.empty(pkg.list_bound(lo, hi), dtype=torch.int64, pin_memory=True)
+    s.list_host(lo, lo + 10 ** 8, elem_bytes=8, out=host)  # warm-up: pipeline buffers
+    t1 = time.perf_counter()
+    n = len(s.list_host(lo, hi, elem_bytes=8, out=host))
+    dt_host = time.perf_counter() - t1
+    s.close()
+    return {"generator": {"workload": "sieve_gen_next of 2^24 uint64 primes per call from 10^12",
+                          "ms_per_call": round(dt_gen * 1e3, 3),
+                          "primes_per_s": round((1 << 24) / dt_gen, 1), "position_after": pos},
+            "list_host": {"workload": "uint64 list of [10^12, 10^12 + 10^10) streamed to pinned host memory",
+                          "primes": n, "ms": round(dt_host * 1e3, 3), "primes_per_s": round(n / dt_host, 1),
+                          "host_GB_per_s": round(8 * n / dt_host / 1e9, 2)}}
 
 
 def bench_serve(pkg, workloads):
@@ -287,9 +348,11 @@ def main() -> int:
     lds_bytes = 4 * marks + 16 * words
     k_ms = sieve_ms / max(jobs, 1)
     achieved = lds_bytes / (k_ms * 1e-3) / 1e9
+    tr = measured_traffic() if hi == 10 ** 11 + 1 else None
     roof = {"bound": "alu", "resource": "LDS read-modify-write (32-bit words)",
             "achieved": round(achieved, 1), "peak": round(LDS_PEAK_GBS, 1), "unit": "GB/s",
-            "frac": round(achieved / LDS_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / LDS_PEAK_GBS, 4),
+            "traffic": (tr["fetch_bytes"] + tr["write_bytes"]) if tr else None,
             "kernel": "k_sieve", "kernel_ms": round(k_ms, 4), "marks": marks,
             "algorithmic_bytes": lds_bytes}
 
@@ -298,11 +361,19 @@ def main() -> int:
     if not args.no_extras:
         from paper_2310_17746_amd import workloads
         extras = {}
+        from paper_2310_17746_amd import autotune
+        print("bench: autotune batch", file=sys.stderr, flush=True)
+        tuned = autotune.tune("batch")
+        bparams = dict(params, **tuned["params"])
         for name, fn in (("list_1e9", lambda: bench_list(pkg, torch, params)),
-                         ("batch_4096", lambda: bench_batch(pkg, torch, params, workloads)),
+                         ("batch_4096", lambda: bench_batch(pkg, torch, bparams, workloads)),
+                         ("stream", lambda: bench_stream(pkg, torch, params)),
                          ("serve_2000", lambda: bench_serve(pkg, workloads))):
             print("bench: %s" % name, file=sys.stderr, flush=True)
             extras[name] = fn()
+        extras["batch_4096"]["autotune"] = {"chosen": tuned["params"], "sample_ms": round(tuned["ms"], 3),
+                                            "default_sample_ms": round(tuned["default_ms"], 3),
+                                            "candidates": len(tuned["grid"])}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -52,6 +52,7 @@ extern "C" {
 #define SIEVE_E_DEVICE (-6)    /* HIP runtime error, no device, wrong architecture */
 #define SIEVE_E_BUSY (-7)      /* server queue full */
 #define SIEVE_E_CANCELLED (-8) /* request cancelled before it finished */
+#define SIEVE_E_IO (-9)        /* a file could not be created or written */
 
 /* Largest accepted hi (ranges are [lo, hi) with hi <= 2^63). */
 #define SIEVE_MAX_HI ((uint64_t)1 << 63)
@@ -219,6 +220,67 @@ int sieve_plan_range(uint64_t lo, uint64_t hi, uint32_t segment_bytes, uint64_t 
 int sieve_set_timing(sieve_ctx *ctx, int on);
 int sieve_get_timing(const sieve_ctx *ctx, double *sieve_ms, double *post_ms, double *bucket_ms,
                      uint64_t *jobs);
+
+/* ------------------------------------------------------------------------
+ * Incremental generation (Sec. 2.4: the sieve keeps producing primes from
+ * where it stopped, and the Sieve Data Store of Sec. 4 grows as the squares
+ * of new primes are reached).  A generator hands out the primes >= start in
+ * increasing order, n at a time, with no upper limit fixed in advance.  It
+ * sieves blocks of whole tiles ahead of its cursor into a device staging
+ * buffer it owns and extends the context's base primes as needed.
+ * ------------------------------------------------------------------------ */
+typedef struct sieve_gen sieve_gen;
+
+/* Creates a generator on ctx starting at value `start`, handing out elements
+ * of elem_bytes (4: its value domain ends at 2^32; 8: at SIEVE_MAX_HI).
+ * start beyond the domain end is SIEVE_E_INVAL.  The generator borrows ctx:
+ * ctx must outlive it and calls on the two must not overlap. */
+int sieve_gen_create(sieve_ctx *ctx, uint64_t start, int elem_bytes, sieve_gen **gen);
+
+/* Writes the next n primes of the generator in increasing order to out_dev
+ * (device memory owned by the caller, room for n elements) and advances past
+ * them.  *n_out receives the number written: n, or fewer once the end of the
+ * value domain is reached (later calls write 0).  Synchronous on `stream`
+ * (NULL: the context stream). */
+int sieve_gen_next(sieve_gen *gen, uint64_t n, void *out_dev, uint64_t *n_out, void *stream);
+
+/* *next receives the generator's position: every prime below it has been
+ * handed out and none at or above it (the start value before the first
+ * prime; the domain end once exhausted). */
+int sieve_gen_position(const sieve_gen *gen, uint64_t *next);
+
+/* Frees the generator (NULL is accepted); the context is not affected. */
+int sieve_gen_destroy(sieve_gen *gen);
+
+/* ------------------------------------------------------------------------
+ * Streaming output to the host and to files (the Prime Number Data Store of
+ * Sec. 4, written out to files as Sec. 6 proposes).  The range is cut into
+ * pieces whose rigorous prime bound (sieve_list_bound) is at most
+ * piece_elems (0: 2^24 elements; at least 256); piece k+1 is sieved on the
+ * context stream while piece k is copied to the host on a second stream and
+ * piece k-1 is consumed by a host task.  The context keeps two device and
+ * two pinned host buffers of piece_elems elements between calls.  Base
+ * primes must cover isqrt(hi - 1) as for sieve_list.
+ * ------------------------------------------------------------------------ */
+
+/* Lists the primes of [lo, hi) in increasing order into out_host (host
+ * memory owned by the caller, pageable or pinned; pinned memory is written by
+ * DMA directly).  *n_out receives the count.  If it exceeds cap the call
+ * returns SIEVE_E_CAPACITY, *n_out holds the required count and the contents
+ * of out_host are unspecified.  elem_bytes 4 needs hi - 1 <= 2^32 - 1. */
+int sieve_list_host(sieve_ctx *ctx, uint64_t lo, uint64_t hi, void *out_host, uint64_t cap,
+                    int elem_bytes, uint64_t piece_elems, uint64_t *n_out);
+
+/* Writes the primes of [lo, hi) in increasing order to the files
+ * "<path_prefix>.000000", "<path_prefix>.000001", ... as raw little-endian
+ * elements of elem_bytes.  Every file but the last holds exactly
+ * primes_per_file primes (0: 125,000,000); an empty range creates no file.
+ * *n_out receives the count and *n_files the number of files created.
+ * SIEVE_E_IO when a file cannot be created or written (files written so far
+ * stay in place). */
+int sieve_write_files(sieve_ctx *ctx, uint64_t lo, uint64_t hi, const char *path_prefix,
+                      uint64_t primes_per_file, int elem_bytes, uint64_t piece_elems,
+                      uint64_t *n_out, uint64_t *n_files);
 
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of range queries.

@@ -19,7 +19,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Sieve", "Server", "SieveError", "Params", "list_bound", "wheel_start", "plan_range", "probe_lds",
+__all__ = ["Sieve", "Server", "Generator", "SieveError", "Params", "list_bound", "wheel_start", "plan_range", "probe_lds",
            "lib_path", "load_library", "SIEVE_OK", "SIEVE_E_CAPACITY"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -35,6 +35,7 @@ SIEVE_E_NOMEM = -5
 SIEVE_E_DEVICE = -6
 SIEVE_E_BUSY = -7
 SIEVE_E_CANCELLED = -8
+SIEVE_E_IO = -9
 PRESIEVE_NONE = 0xFFFFFFFF
 BUCKET_NEVER = 0xFFFFFFFF
 BUCKET_EXACT = 1
@@ -140,6 +141,14 @@ def load_library():
         "sieve_server_get_stats": (ctypes.c_int, [_p, ctypes.POINTER(ServerStats)]),
         "sieve_server_now_ns": (_u64, [_p]),
         "sieve_server_destroy": (ctypes.c_int, [_p]),
+        "sieve_gen_create": (ctypes.c_int, [_p, _u64, ctypes.c_int, ctypes.POINTER(_p)]),
+        "sieve_gen_next": (ctypes.c_int, [_p, _u64, _p, ctypes.POINTER(_u64), _p]),
+        "sieve_gen_position": (ctypes.c_int, [_p, ctypes.POINTER(_u64)]),
+        "sieve_gen_destroy": (ctypes.c_int, [_p]),
+        "sieve_list_host": (ctypes.c_int, [_p, _u64, _u64, _p, _u64, ctypes.c_int, _u64,
+                                           ctypes.POINTER(_u64)]),
+        "sieve_write_files": (ctypes.c_int, [_p, _u64, _u64, ctypes.c_char_p, _u64, ctypes.c_int, _u64,
+                                             ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -298,6 +307,43 @@ class Sieve:
         _check(code, "sieve_list")
         return out[: n.value]
 
+    def list_host(self, lo: int, hi: int, elem_bytes: int = 8, out=None, piece_elems: int = 0):
+        """Primes of [lo, hi) streamed into host memory.
+
+        `out` may be a numpy array or a (pinned) CPU torch tensor with
+        elem_bytes-byte elements; by default a numpy array of the rigorous
+        bound is allocated.  Returns the filled prefix.
+        """
+        if out is None:
+            out = np.empty(max(list_bound(lo, hi), 1), dtype=np.uint32 if elem_bytes == 4 else np.uint64)
+        if isinstance(out, np.ndarray):
+            if out.itemsize != elem_bytes or not out.flags["C_CONTIGUOUS"]:
+                raise ValueError("out must be contiguous with %d-byte elements" % elem_bytes)
+            ptr, cap = out.ctypes.data, out.size
+        else:
+            if out.element_size() != elem_bytes or not out.is_contiguous() or out.is_cuda:
+                raise ValueError("out must be a contiguous host tensor with %d-byte elements" % elem_bytes)
+            ptr, cap = out.data_ptr(), out.numel()
+        n = _u64()
+        code = self._lib.sieve_list_host(self._h, lo, hi, ptr, cap, elem_bytes, piece_elems, ctypes.byref(n))
+        if code == SIEVE_E_CAPACITY:
+            raise SieveError(code, "sieve_list_host needs %d elements" % n.value)
+        _check(code, "sieve_list_host")
+        return out[: n.value]
+
+    def write_files(self, lo: int, hi: int, path_prefix: str, primes_per_file: int = 0,
+                    elem_bytes: int = 8, piece_elems: int = 0) -> tuple[int, int]:
+        """Writes the primes of [lo, hi) to <prefix>.000000, ...; returns (count, files)."""
+        n, nf = _u64(), _u64()
+        _check(self._lib.sieve_write_files(self._h, lo, hi, os.fsencode(path_prefix), primes_per_file,
+                                           elem_bytes, piece_elems, ctypes.byref(n), ctypes.byref(nf)),
+               "sieve_write_files")
+        return n.value, nf.value
+
+    def generator(self, start: int = 0, elem_bytes: int = 8) -> "Generator":
+        """An incremental generator of the primes >= start (see Generator)."""
+        return Generator(self, start, elem_bytes)
+
     def count_list(self, lo: int, hi: int, elem_bytes: int = 8) -> int:
         """Count through the list path without an output buffer (cap 0)."""
         n = _u64()
@@ -349,6 +395,57 @@ class Sieve:
         _check(self._lib.sieve_get_timing(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
                                           ctypes.byref(n)), "sieve_get_timing")
         return a.value, b.value, c.value, n.value
+
+
+class Generator:
+    """Hands out the primes from `start` on, n at a time, as device tensors.
+
+    Keeps a reference to its Sieve; the two must not be used concurrently.
+    """
+
+    def __init__(self, sieve: "Sieve", start: int = 0, elem_bytes: int = 8):
+        self._sieve = sieve
+        self._lib = sieve._lib
+        self.elem_bytes = elem_bytes
+        h = _p()
+        _check(self._lib.sieve_gen_create(sieve._h, start, elem_bytes, ctypes.byref(h)), "sieve_gen_create")
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.sieve_gen_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def position(self) -> int:
+        v = _u64()
+        _check(self._lib.sieve_gen_position(self._h, ctypes.byref(v)), "sieve_gen_position")
+        return v.value
+
+    def next(self, n: int, out=None, stream=None):
+        """The next n primes (fewer at the end of the value domain)."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(max(n, 1), dtype=_dtype_for(self.elem_bytes),
+                              device="cuda:%d" % self._sieve.device)
+        if out.element_size() != self.elem_bytes or not out.is_contiguous() or out.numel() < n:
+            raise ValueError("out must be contiguous with room for %d %d-byte elements" % (n, self.elem_bytes))
+        got = _u64()
+        _check(self._lib.sieve_gen_next(self._h, n, out.data_ptr(), ctypes.byref(got), _stream_handle(stream)),
+               "sieve_gen_next")
+        return out[: got.value]
 
 
 class Server:

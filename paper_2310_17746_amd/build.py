@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsieve.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.hip", "kernels.hip", "server.hip", "lds_probe.hip"]
+SOURCES = ["api.hip", "kernels.hip", "server.hip", "stream.hip", "lds_probe.hip"]
 
 COMMON = [
     "--offload-arch=gfx950",

@@ -267,8 +267,7 @@ void plan_range(uint64_t lo, uint64_t hi, uint32_t pw, uint64_t &ntiles, uint64_
 
 struct Plan {
     std::vector<RangeDesc> ranges;
-    std::vector<uint32_t> list_idx;
-    std::vector<uint64_t> list_chunk0;
+    uint64_t nlist = 0;  // ranges in list mode
     uint64_t ntiles = 0, nchunks = 0, nunits = 0;
     uint64_t best = 0;  // bucket entries of the estimated layout
 };
@@ -337,8 +336,7 @@ int make_plan(const sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t
             d.nchunks = (uint32_t)nch;
             d.chunk0 = pl.nchunks;
             pl.nchunks += nch;
-            pl.list_idx.push_back((uint32_t)i);
-            pl.list_chunk0.push_back(d.chunk0);
+            pl.nlist++;
         }
     }
     return SIEVE_OK;
@@ -347,16 +345,14 @@ int make_plan(const sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct BlobLayout {
-    size_t ranges, list_idx, list_chunk0, total;
+    size_t ranges, total;
 };
 
-BlobLayout blob_layout(uint64_t nranges, uint64_t nlist)
+BlobLayout blob_layout(uint64_t nranges)
 {
     BlobLayout L;
     L.ranges = align_up(sizeof(JobHeader), 256);
-    L.list_idx = align_up(L.ranges + sizeof(RangeDesc) * std::max<uint64_t>(nranges, 1), 256);
-    L.list_chunk0 = align_up(L.list_idx + sizeof(uint32_t) * std::max<uint64_t>(nlist, 1), 256);
-    L.total = align_up(L.list_chunk0 + sizeof(uint64_t) * std::max<uint64_t>(nlist, 1), 256);
+    L.total = align_up(L.ranges + sizeof(RangeDesc) * std::max<uint64_t>(nranges, 1), 256);
     return L;
 }
 
@@ -369,13 +365,12 @@ uint64_t grow(uint64_t cur, uint64_t need, uint64_t floor_)
 
 // Makes the scratch hold a job of the given size.  Capacities only grow; any
 // reallocation bumps c->gen so that captured graphs are re-made.
-int ensure_capacity(sieve_ctx *c, uint64_t nranges, uint64_t nlist, uint64_t nchunks, uint64_t ntiles)
+int ensure_capacity(sieve_ctx *c, uint64_t nranges, uint64_t nchunks, uint64_t ntiles)
 {
     bool changed = false;
-    if (nranges > c->cap_ranges || nlist > c->cap_list || !c->d_blob.p) {
+    if (nranges > c->cap_ranges || !c->d_blob.p) {
         c->cap_ranges = grow(c->cap_ranges, nranges, 64);
-        c->cap_list = grow(c->cap_list, nlist, 64);
-        const BlobLayout L = blob_layout(c->cap_ranges, c->cap_list);
+        const BlobLayout L = blob_layout(c->cap_ranges);
         c->d_blob.release();
         c->d_counts.release();
         c->d_status.release();
@@ -406,9 +401,10 @@ int ensure_capacity(sieve_ctx *c, uint64_t nranges, uint64_t nlist, uint64_t nch
         c->cap_chunks = grow(c->cap_chunks, nchunks, 64);
         c->d_bitmap.release();
         c->d_chunk_counts.release();
+        c->d_chunk_range.release();
         c->d_chunk_off.release();
         if (!c->d_bitmap.reserve(c->cap_chunks * kChunkWords) || !c->d_chunk_counts.reserve(c->cap_chunks) ||
-            !c->d_chunk_off.reserve(c->cap_chunks))
+            !c->d_chunk_range.reserve(c->cap_chunks) || !c->d_chunk_off.reserve(c->cap_chunks))
             return SIEVE_E_NOMEM;
         changed = true;
     }
@@ -454,7 +450,7 @@ enum Phase { kPhaseWhole = 0, kPhaseBucketCount = 1, kPhaseRest = 2, kPhaseDirec
 //   rest:          exact bucket fill, sieve, finalize, compact
 hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed)
 {
-    const BlobLayout L = blob_layout(c->cap_ranges, c->cap_list);
+    const BlobLayout L = blob_layout(c->cap_ranges);
     const JobHeader *job = (const JobHeader *)c->d_blob.p;
     const RangeDesc *ranges = (const RangeDesc *)(c->d_blob.p + L.ranges);
     const uint32_t pw = c->prm.segment_bytes / 8;
@@ -526,6 +522,7 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed)
     a.skip5 = (c->ngroups >= 1 && c->prm.cofactor_skip == SIEVE_SKIP_ALL) ? 1u : 0u;
     a.bitmap = c->d_bitmap.p;
     a.chunk_counts = c->d_chunk_counts.p;
+    a.chunk_range = c->d_chunk_range.p;
     a.bdata = c->d_bdata.p;
     a.boff = c->d_boff.p;
     a.bcount = c->d_bcount.p;
@@ -549,8 +546,7 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed)
     CompactArgs k;
     k.job = job;
     k.ranges = ranges;
-    k.list_idx = (const uint32_t *)(c->d_blob.p + L.list_idx);
-    k.list_chunk0 = (const uint64_t *)(c->d_blob.p + L.list_chunk0);
+    k.chunk_range = c->d_chunk_range.p;
     k.status = c->d_status.p;
     k.bitmap = c->d_bitmap.p;
     k.chunk_off = c->d_chunk_off.p;
@@ -613,14 +609,14 @@ int run_job(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, co
     int st = make_plan(c, n, lo, hi, mode, off, cap, elem_bytes, pl);
     if (st != SIEVE_OK)
         return st;
-    const uint64_t nlist = pl.list_idx.size();
+    const uint64_t nlist = pl.nlist;
     if (nlist && !out)
         return SIEVE_E_INVAL;
-    st = ensure_capacity(c, n, nlist, pl.nchunks, pl.ntiles);
+    st = ensure_capacity(c, n, pl.nchunks, pl.ntiles);
     if (st != SIEVE_OK)
         return st;
     hipStream_t s = stream ? stream : c->stream;
-    const BlobLayout L = blob_layout(c->cap_ranges, c->cap_list);
+    const BlobLayout L = blob_layout(c->cap_ranges);
     JobHeader *h = (JobHeader *)c->h_blob;
     memset(h, 0, sizeof *h);
     h->ntiles = pl.ntiles;
@@ -633,15 +629,8 @@ int run_job(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, co
     h->elem_bytes = elem_bytes;
     if (n)
         memcpy(c->h_blob + L.ranges, pl.ranges.data(), n * sizeof(RangeDesc));
-    if (nlist) {
-        memcpy(c->h_blob + L.list_idx, pl.list_idx.data(), nlist * sizeof(uint32_t));
-        memcpy(c->h_blob + L.list_chunk0, pl.list_chunk0.data(), nlist * sizeof(uint64_t));
-    }
     hipError_t e = hipMemcpyAsync(c->d_blob.p, c->h_blob, L.ranges + n * sizeof(RangeDesc),
                                   hipMemcpyHostToDevice, s);
-    if (e == hipSuccess && nlist)
-        e = hipMemcpyAsync(c->d_blob.p + L.list_idx, c->h_blob + L.list_idx,
-                           L.list_chunk0 - L.list_idx + nlist * sizeof(uint64_t), hipMemcpyHostToDevice, s);
     if (e != hipSuccess)
         return hip_status(e);
     const bool buckets = pl.nunits != 0;
@@ -799,6 +788,7 @@ void destroy_ctx(sieve_ctx *c)
     c->d_status.release();
     c->d_bitmap.release();
     c->d_chunk_counts.release();
+    c->d_chunk_range.release();
     c->d_chunk_off.release();
     if (c->h_blob)
         (void)hipHostFree(c->h_blob);
@@ -811,6 +801,15 @@ void destroy_ctx(sieve_ctx *c)
     for (auto &ev : c->ev)
         if (ev)
             (void)hipEventDestroy(ev);
+    for (int i = 0; i < 2; ++i) {
+        c->d_piece[i].release();
+        if (c->h_piece[i])
+            (void)hipHostFree(c->h_piece[i]);
+        if (c->piece_ev[i])
+            (void)hipEventDestroy(c->piece_ev[i]);
+    }
+    if (c->copy_stream)
+        (void)hipStreamDestroy(c->copy_stream);
     if (c->stream)
         (void)hipStreamDestroy(c->stream);
     delete c;
@@ -860,6 +859,8 @@ const char *sieve_strerror(int s)
         return "busy";
     case SIEVE_E_CANCELLED:
         return "cancelled";
+    case SIEVE_E_IO:
+        return "file I/O error";
     default:
         return "unknown status";
     }
@@ -930,7 +931,7 @@ int sieve_create(sieve_ctx **out, int device, const sieve_params *p)
     if (st == SIEVE_OK)
         st = install_primes(c, 0);
     if (st == SIEVE_OK)
-        st = ensure_capacity(c, 1, 1, 1, 1);
+        st = ensure_capacity(c, 1, 1, 1);
     if (st != SIEVE_OK) {
         destroy_ctx(c);
         return st;
@@ -1081,8 +1082,10 @@ int sieve_wheel_start(uint64_t p, uint64_t base, uint64_t M, int64_t *id1, int64
     if (!id1 || !id5 || p < 5 || (p % 6 != 1 && p % 6 != 5) || base % 6 || M < 1 || M < base ||
         M - base >= (1ull << 22) || p >= (1ull << 32))
         return SIEVE_E_INVAL;
+    // The same remainder path as the kernels (invariant reciprocal).
     uint32_t a, b;
-    wheel_start((uint32_t)p, (uint32_t)(p / 6), UINT64_MAX / p, base, M, p < 0x80000000ull, a, b);
+    const uint32_t rem = mod_invariant(M - 1, (uint32_t)p, UINT64_MAX / p, p < 0x80000000ull);
+    wheel_start((uint32_t)p, (uint32_t)(p / 6), base, M, rem, a, b);
     *id1 = a;
     *id5 = b;
     return SIEVE_OK;

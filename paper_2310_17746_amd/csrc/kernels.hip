@@ -287,7 +287,8 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
                     continue;
                 uint32_t id1, id5;
                 const uint32_t R = pc.r & 0x1FFFFFFFu, inv5 = pc.r >> 29;
-                wheel_start(pc.p, R, ((uint64_t)pc.m_hi << 32) | pc.m_lo, B, M, narrow, id1, id5);
+                const uint32_t rem = start_rem(pc, B, P2, narrow);
+                wheel_start(pc.p, R, B, M, rem, id1, id5);
                 const uint32_t step = g * pc.p;
                 const uint32_t off = j * pc.p;
                 if (a.skip5) {
@@ -375,8 +376,10 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
             __syncthreads();
             const uint32_t nch = nw_pad / kChunkWords;
             const uint64_t cbase = d.chunk0 + k * (pw / kChunkWords);
-            if (tid < nch)
+            if (tid < nch) {
                 a.chunk_counts[cbase + tid] = sh.chunk[tid];
+                a.chunk_range[cbase + tid] = rix;
+            }
         } else {
             cnt = wave_sum(cnt);
             if (lane == 0)
@@ -457,7 +460,9 @@ __device__ inline HitWalk walk_init(const BucketArgs &a, const RangeDesc &d, uin
     const uint64_t Bt = d.base + tM * a.span;
     uint32_t id1, id5;
     const uint32_t R = pc.r & 0x1FFFFFFFu, inv5 = pc.r >> 29;
-    wheel_start(pc.p, R, ((uint64_t)pc.m_hi << 32) | pc.m_lo, Bt, M, rend <= (1ull << 62), id1, id5);
+    // (M - 1) mod P: M is P^2 or the window base (the tile base Bt then)
+    const uint32_t rem = start_rem(pc, wbase, P2, rend <= (1ull << 62));
+    wheel_start(pc.p, R, Bt, M, rem, id1, id5);
     if (a.skip5) {
         const uint32_t bt5 = (uint32_t)(Bt % 5);
         w.c1 = cofactor_mod5(bt5, id1, 1, inv5);
@@ -705,19 +710,9 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(CompactArgs a)
     if (a.job->elem_bytes != (int32_t)sizeof(T))
         return;
     const uint64_t nchunks = a.job->nchunks;
-    const uint32_t nlist = a.job->nlist;
 
     for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-        // List range holding chunk c: the last one whose chunk0 <= c.
-        uint32_t lo = 0, hi = nlist;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (a.list_chunk0[mid] <= c)
-                lo = mid;
-            else
-                hi = mid;
-        }
-        const uint32_t r = a.list_idx[lo];
+        const uint32_t r = a.chunk_range[c];  // written by the sieve kernel
         if (a.status[r] != 0)
             continue;  // over capacity: nothing is written for this range
         const RangeDesc &d = a.ranges[r];

@@ -81,19 +81,20 @@ struct sieve_ctx {
     uint32_t restore1 = 0, restore5 = 0;
 
     // Job scratch.
-    sieve::rt::DevBuf<unsigned char> d_blob;  // JobHeader | RangeDesc[] | list_idx[] | list_chunk0[]
+    sieve::rt::DevBuf<unsigned char> d_blob;  // JobHeader | RangeDesc[]
     sieve::rt::DevBuf<unsigned long long> d_counters;
     sieve::rt::DevBuf<unsigned long long> d_counts;
     sieve::rt::DevBuf<int32_t> d_status;
     sieve::rt::DevBuf<unsigned long long> d_bitmap;
     sieve::rt::DevBuf<uint32_t> d_chunk_counts;
+    sieve::rt::DevBuf<uint32_t> d_chunk_range;
     sieve::rt::DevBuf<unsigned long long> d_chunk_off;
     unsigned char *h_blob = nullptr;  // pinned staging for the blob
     size_t h_blob_n = 0;
     unsigned long long *h_counts = nullptr;  // pinned
     int32_t *h_status = nullptr;             // pinned
     unsigned long long *h_flag = nullptr;    // pinned copy of the error and overflow flags
-    uint64_t cap_ranges = 0, cap_list = 0, cap_chunks = 0;
+    uint64_t cap_ranges = 0, cap_chunks = 0;
 
     // Bucket sieve scratch: per-tile counts, cursors and offsets; entries.
     sieve::rt::DevBuf<uint32_t> d_bcount, d_bcursor, d_bdata;
@@ -109,6 +110,15 @@ struct sieve_ctx {
     hipGraph_t graph_src[4] = {nullptr, nullptr, nullptr, nullptr};
     uint64_t graph_gen[4] = {~0ull, ~0ull, ~0ull, ~0ull};
     uint64_t gen = 0;
+
+    // Host streaming (stream.hip): two device piece buffers, two pinned
+    // staging buffers, a copy stream and one event per slot, kept between
+    // calls.
+    sieve::rt::DevBuf<unsigned char> d_piece[2];
+    unsigned char *h_piece[2] = {nullptr, nullptr};
+    size_t h_piece_bytes = 0;
+    hipStream_t copy_stream = nullptr;
+    hipEvent_t piece_ev[2] = {nullptr, nullptr};
 
     // Optional event timing of the sieve kernel and the post-processing.
     int timing = 0;

@@ -107,6 +107,7 @@ struct SieveArgs {
     uint32_t skip5;               // 1: multiples of 5 are presieved, so no mark with 5 | cofactor
     unsigned long long *bitmap;   // list scratch (u64 words)
     uint32_t *chunk_counts;       // per chunk prime count
+    uint32_t *chunk_range;        // per chunk: index of its range
     const uint32_t *bdata;        // bucket entries: bit | plane << 31
     const unsigned long long *boff;  // exact layout, per tile: first entry
     const uint32_t *bcount;       // exact layout, per tile: entries
@@ -150,8 +151,7 @@ struct FinalizeArgs {
 struct CompactArgs {
     const JobHeader *job;
     const RangeDesc *ranges;
-    const uint32_t *list_idx;     // range index of each list range, ascending chunk0
-    const uint64_t *list_chunk0;  // chunk0 of each list range
+    const uint32_t *chunk_range;  // per chunk: index of its range
     const int32_t *status;
     const unsigned long long *bitmap;
     const unsigned long long *chunk_off;

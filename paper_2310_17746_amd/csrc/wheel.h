@@ -11,15 +11,16 @@
 // M is max(B, P*P): marking starts at the square (Sec. 1.1, Sec. 2.4), which
 // also keeps a segment that holds P itself from clearing it.
 //
-// Arithmetic.  The one wide step is x mod P for the 64-bit x = M - 1; it uses
-// a per-prime reciprocal m = floor((2^64 - 1) / P): mulhi64(x, m) is
-// floor(x / P) or one less (m is below 2^64 / P by less than 1, so
-// x * m / 2^64 > x / P - 1), and one conditional subtraction of P corrects it
-// (Granlund and Montgomery, PLDI 1994, division by invariant integers using
-// multiplication).  Everything after it fits in 32 bits: d = Q - B lies in
-// [-P, 2^22) for a tile, so d + 6(R + 1) (> P) is non-negative and below
-// 2^32 for every P < 3.1e9, and floor division of that biased value by 6
-// gives idx0 + R + 1 and q = Q mod 6 without signed 64-bit division.
+// Arithmetic.  The one wide step is rem = (M - 1) mod P.  When M = P*P it
+// is simply P - 1.  Otherwise it uses a per-prime reciprocal
+// m = floor((2^64 - 1) / P): mulhi64(x, m) is floor(x / P) or one less (m is
+// below 2^64 / P by less than 1, so x * m / 2^64 > x / P - 1), and one
+// conditional subtraction of P corrects it (Granlund and Montgomery, PLDI
+// 1994, division by invariant integers using multiplication).  Everything
+// after the remainder fits in 32 bits: d = Q - B lies in [-P, 2^22) for a
+// tile, so d + 6(R + 1) (> P) is non-negative and below 2^32 for every
+// P < 3.1e9, and floor division of that biased value by 6 gives
+// idx0 + R + 1 and q = Q mod 6 without signed 64-bit division.
 #pragma once
 
 #include <stdint.h>
@@ -66,7 +67,7 @@ __host__ __device__ inline uint32_t inv_mod5(uint32_t x)
     return (0x42310u >> (4u * (x % 5u))) & 0xFu;  // 0->0, 1->1, 2->3, 3->2, 4->4
 }
 
-__host__ __device__ inline PrimeConst make_prime_const(uint32_t p)
+inline PrimeConst make_prime_const(uint32_t p)
 {
     const uint64_t m = UINT64_MAX / p;
     return PrimeConst{p, (p / 6u) | (inv_mod5(p) << 29), (uint32_t)m, (uint32_t)(m >> 32)};
@@ -95,15 +96,22 @@ __host__ __device__ inline uint32_t mod_invariant(uint64_t x, uint32_t P, uint64
     return (uint32_t)(r >= P ? r - P : r);
 }
 
-// Start indices (relative to base B) of prime P in both planes for a first
-// value M with B <= M < B + 2^22 and M >= 1.  Both results are the true
-// indices (>= 0); callers compare them against the plane length.  `narrow`
-// must be true only when P < 2^31.
-__host__ __device__ inline void wheel_start(uint32_t P, uint32_t R, uint64_t m, uint64_t B, uint64_t M,
-                                            bool narrow, uint32_t &id1, uint32_t &id5)
+// (M - 1) mod P for M = max(B, P * P); `narrow` as for mod_invariant.
+__host__ __device__ inline uint32_t start_rem(const PrimeConst &pc, uint64_t B, uint64_t P2, bool narrow)
 {
-    const uint64_t x = M - 1;
-    const uint32_t rem = mod_invariant(x, P, m, narrow);  // Q = x - rem, greatest multiple below M
+    if (P2 > B)
+        return pc.p - 1u;  // (P^2 - 1) mod P
+    return mod_invariant(B - 1, pc.p, ((uint64_t)pc.m_hi << 32) | pc.m_lo, narrow);
+}
+
+// Start indices (relative to base B) of prime P in both planes for a first
+// value M with B <= M < B + 2^22 and M >= 1, given rem = (M - 1) mod P.
+// Both results are the true indices (>= 0); callers compare them against
+// the plane length.
+__host__ __device__ inline void wheel_start(uint32_t P, uint32_t R, uint64_t B, uint64_t M, uint32_t rem,
+                                            uint32_t &id1, uint32_t &id5)
+{
+    const uint64_t x = M - 1;  // Q = x - rem, the greatest multiple of P below M
     // dp = (Q - B) + 6(R + 1), computed mod 2^32 (its true value is in [1, 2^32)).
     const uint32_t dp = (uint32_t)(x - B) - rem + 6u * (R + 1u);
     const uint32_t i0 = dp / 6u;       // = idx0 + R + 1

@@ -117,3 +117,34 @@ def test_list_bound_is_an_upper_bound():
         assert b >= c, (lo, hi, b, c)
         if hi - lo > 10 ** 5:
             assert b <= 6 * c + 100  # not vacuous (2y/ln y vs y/ln x)
+
+
+def test_table1_remainder_edges():
+    """The library's remainder of M - 1 by P (invariant reciprocal, 32-bit
+    correction below P = 2^31): bases at multiples of P and one off, near
+    2^52 and near P^2, all against the oracle's definition."""
+    from oracle import brute
+    rng = random.Random(23)
+    big = [p for p in range(2 ** 30 - 200, 2 ** 30) if brute.is_prime_mr(p)][-3:]
+    big += [p for p in range(2 ** 29 - 100, 2 ** 29 + 100) if brute.is_prime_mr(p)][:3]
+    small = [5, 7, 67, 1009, 65537, 31622771]
+    n = 0
+    for P in small + big:
+        bases = []
+        for top in (2 ** 52, 2 ** 52 - 6 * 1000, 10 ** 15, 6 * 10 ** 12):
+            k = top // P
+            for mult in (k - 1, k, k + 1):
+                for d in (-7, -1, 0, 1, 5, 6):
+                    b = (mult * P + d) // 6 * 6
+                    if b >= 0:
+                        bases.append(b)
+        bases += [6 * rng.randrange(0, 2 ** 49) for _ in range(20)]
+        for base in bases:
+            M = max(base, P * P) if P * P - base < 2 ** 22 else base
+            M = max(M, 1)
+            got = pkg.wheel_start(P, base, M)
+            want = (wheel.first_multiple_index(P, base, M, 1),
+                    wheel.first_multiple_index(P, base, M, 5))
+            assert got == want, (P, base, M)
+            n += 1
+    assert n > 1000
