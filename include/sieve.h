@@ -91,6 +91,10 @@ typedef struct sieve_ctx sieve_ctx;
  *                    presieve): 0 (default) in the bucket sieve only;
  *                    SIEVE_SKIP_ALL also in the per-tile marking loop;
  *                    SIEVE_SKIP_NONE nowhere.  Needs presieve_groups >= 1.
+ *   bucket_mem_mb    device memory one job may use for bucket entries, in
+ *                    MiB (default 4096).  A job whose estimate is larger runs
+ *                    as a sequence of jobs over tile-aligned pieces of its
+ *                    ranges; results are the same.
  */
 typedef struct sieve_params {
     uint32_t segment_bytes;
@@ -102,7 +106,7 @@ typedef struct sieve_params {
     uint32_t use_graph;
     uint32_t bucket_slices;
     uint32_t cofactor_skip;
-    uint32_t reserved;
+    uint32_t bucket_mem_mb;
 } sieve_params;
 
 #define SIEVE_PRESIEVE_NONE 0xFFFFFFFFu

@@ -53,10 +53,10 @@ class Params(ctypes.Structure):
                 ("presieve_groups", ctypes.c_uint32), ("split_hits", ctypes.c_uint32),
                 ("bucket_threshold", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32),
                 ("use_graph", ctypes.c_uint32), ("bucket_slices", ctypes.c_uint32),
-                ("cofactor_skip", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("cofactor_skip", ctypes.c_uint32), ("bucket_mem_mb", ctypes.c_uint32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class ServerParams(ctypes.Structure):

@@ -27,7 +27,7 @@ CACHE = os.environ.get("SIEVE_AUTOTUNE_CACHE",
 
 # Candidate grids per workload class: (segment_bytes, block_threads, wg_per_cu, split_hits,
 # bucket_threshold).  bucket_threshold 0 = automatic.
-_SEGS = [(32768, 512, 4), (40960, 512, 3), (49152, 512, 3), (65536, 512, 2), (159744, 1024, 1)]
+_SEGS = [(32768, 512, 4), (49152, 512, 3), (53248, 512, 3), (77824, 512, 2), (159744, 1024, 1)]
 GRIDS = {
     "count": [dict(segment_bytes=sg, block_threads=nt, wg_per_cu=w, split_hits=sp)
               for sg, nt, w in _SEGS for sp in (32, 64)],

@@ -92,10 +92,11 @@ int hip_status(hipError_t e)
 
 void fill_defaults(sieve_params &p)
 {
-    // Defaults from the sweep on MI355X (pi(10^11) count): 48 KiB tiles, 512
-    // threads and three workgroups per CU (24 waves), work items of ~32 hits.
+    // Defaults from the sweep on MI355X (pi(10^11) count): 52 KiB tiles (three
+    // fill the 160 KiB of LDS), 512 threads and three workgroups per CU
+    // (24 waves), work items of ~32 hits.
     if (!p.segment_bytes)
-        p.segment_bytes = 48 * 1024;
+        p.segment_bytes = 52 * 1024;
     if (!p.block_threads)
         p.block_threads = 512;
     if (!p.presieve_groups)
@@ -104,6 +105,8 @@ void fill_defaults(sieve_params &p)
         p.split_hits = 32;
     if (!p.wg_per_cu)
         p.wg_per_cu = std::max<uint32_t>(1, std::min<uint32_t>(4, (160 * 1024) / p.segment_bytes));
+    if (!p.bucket_mem_mb)
+        p.bucket_mem_mb = 4096;
 }
 
 int validate_params(const sieve_params &p, uint32_t lds_max)
@@ -601,14 +604,11 @@ hipError_t run_phase(sieve_ctx *c, hipStream_t s, int phase, bool use_graph)
 
 // Runs one job: plan, upload, kernels (graph or direct), results.
 // counts/status (host, n entries) receive per-range results.
-int run_job(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, const uint8_t *mode,
-            const uint64_t *off, const uint64_t *cap, int elem_bytes, void *out, uint64_t *counts,
-            int32_t *status, hipStream_t stream, bool use_graph)
+int run_job_once(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, const uint8_t *mode,
+                 const uint64_t *off, const uint64_t *cap, int elem_bytes, void *out, uint64_t *counts,
+                 int32_t *status, hipStream_t stream, bool use_graph, Plan &pl)
 {
-    Plan pl;
-    int st = make_plan(c, n, lo, hi, mode, off, cap, elem_bytes, pl);
-    if (st != SIEVE_OK)
-        return st;
+    int st;
     const uint64_t nlist = pl.nlist;
     if (nlist && !out)
         return SIEVE_E_INVAL;
@@ -718,6 +718,100 @@ int run_job(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, co
             counts[i] = c->h_counts[i];
         if (status)
             status[i] = c->h_status[i];
+    }
+    return SIEVE_OK;
+}
+
+// Runs a job within the bucket-memory budget.  When the estimated bucket
+// entries of the whole job exceed it, the ranges are cut at tile boundaries
+// of their own plan into pieces (each piece tiles exactly like that part of
+// the range) and the pieces run as a sequence of jobs, at most one piece of
+// a range per job.  Counts add up; a list range's pieces write consecutively
+// (offset and capacity advance by the primes already written), and once a
+// piece does not fit, the rest of that range is only counted and the range
+// reports SIEVE_E_CAPACITY with its full count.
+int run_job(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, const uint8_t *mode,
+            const uint64_t *off, const uint64_t *cap, int elem_bytes, void *out, uint64_t *counts,
+            int32_t *status, hipStream_t stream, bool use_graph)
+{
+    Plan pl;
+    int st = make_plan(c, n, lo, hi, mode, off, cap, elem_bytes, pl);
+    if (st != SIEVE_OK)
+        return st;
+    const uint64_t budget = c->bucket_budget;
+    if (pl.best <= budget)
+        return run_job_once(c, n, lo, hi, mode, off, cap, elem_bytes, out, counts, status, stream, use_graph, pl);
+    if (pl.nlist && !out)
+        return SIEVE_E_INVAL;
+    const uint64_t span = (uint64_t)kValsPerWord * (c->prm.segment_bytes / 8);
+    std::vector<RangeDesc> d0 = pl.ranges;  // the whole ranges' plans
+    std::vector<uint64_t> cur(lo, lo + n), acc(n, 0), tot(n, 0), per(n);
+    std::vector<int32_t> rst(n, SIEVE_OK);
+    for (uint64_t i = 0; i < n; ++i)
+        per[i] = d0[i].bunits ? std::max<uint64_t>(1, budget / std::max<uint32_t>(d0[i].bcap, 1)) : UINT64_MAX;
+    std::vector<uint64_t> glo, ghi, goff, gcap, gcnt, gidx;
+    std::vector<uint8_t> gmode;
+    std::vector<int32_t> gst;
+    uint64_t next = 0;  // first range that may still have work
+    for (;;) {
+        while (next < n && cur[next] >= hi[next])
+            ++next;
+        if (next == n)
+            break;
+        glo.clear(), ghi.clear(), goff.clear(), gcap.clear(), gidx.clear(), gmode.clear();
+        uint64_t used = 0;
+        for (uint64_t i = next; i < n; ++i) {
+            if (cur[i] >= hi[i])
+                continue;
+            const RangeDesc &d = d0[i];
+            uint64_t e = hi[i];
+            uint64_t tiles = d.ntiles;
+            if (per[i] != UINT64_MAX) {
+                // tile k of the range covers [base + k span, base + (k + 1) span)
+                const uint64_t k0 = cur[i] <= d.base ? 0 : (cur[i] - d.base) / span;
+                tiles = std::min<uint64_t>(per[i], d.ntiles - k0);
+                if (k0 + tiles < d.ntiles)
+                    e = d.base + (k0 + tiles) * span;
+            }
+            const uint64_t need = d.bunits ? (uint64_t)d.bcap * tiles : 0;
+            if (!glo.empty() && used + need > budget)
+                break;
+            used += need;
+            const bool lst = mode && mode[i] && rst[i] == SIEVE_OK;
+            glo.push_back(cur[i]);
+            ghi.push_back(e);
+            gmode.push_back(lst ? 1 : 0);
+            goff.push_back(lst ? off[i] + acc[i] : 0);
+            gcap.push_back(lst ? cap[i] - acc[i] : 0);
+            gidx.push_back(i);
+        }
+        const uint64_t m = glo.size();
+        gcnt.assign(m, 0);
+        gst.assign(m, SIEVE_OK);
+        Plan gp;
+        st = make_plan(c, m, glo.data(), ghi.data(), gmode.data(), goff.data(), gcap.data(), elem_bytes, gp);
+        if (st == SIEVE_OK)
+            st = run_job_once(c, m, glo.data(), ghi.data(), gmode.data(), goff.data(), gcap.data(), elem_bytes,
+                              out, gcnt.data(), gst.data(), stream, use_graph, gp);
+        if (st != SIEVE_OK)
+            return st;
+        for (uint64_t g = 0; g < m; ++g) {
+            const uint64_t i = gidx[g];
+            tot[i] += gcnt[g];
+            if (gmode[g]) {
+                if (gst[g] == SIEVE_OK)
+                    acc[i] += gcnt[g];
+                else
+                    rst[i] = gst[g];
+            }
+            cur[i] = ghi[g];
+        }
+    }
+    for (uint64_t i = 0; i < n; ++i) {
+        if (counts)
+            counts[i] = tot[i];
+        if (status)
+            status[i] = rst[i];
     }
     return SIEVE_OK;
 }
@@ -915,6 +1009,7 @@ int sieve_create(sieve_ctx **out, int device, const sieve_params *p)
         return st;
     }
     c->prm = q;
+    c->bucket_budget = (uint64_t)q.bucket_mem_mb * (1u << 20) / sizeof(uint32_t);
     if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
         set_sieve_lds_limit(q.segment_bytes) != hipSuccess) {
         (void)hipGetLastError();

@@ -78,11 +78,11 @@ __device__ __forceinline__ void lds_or(uint32_t byte_addr, uint32_t mask)
 // whose words start at LDS byte `base`.  The paper strides by P indices in
 // each array (Sec. 3: adding P to the index adds 6P to the value and keeps
 // the residue mod 6).
-__device__ __forceinline__ void mark_plane(uint32_t base, uint64_t start, uint32_t step, uint32_t nbits)
+__device__ __forceinline__ void mark_plane(uint32_t base, uint32_t start, uint32_t step, uint32_t nbits)
 {
     if (start >= nbits)
         return;
-    uint32_t i = (uint32_t)start;
+    uint32_t i = start;
     if (step < (nbits >> 2)) {
         const uint32_t lim = nbits - 3 * step;  // i < lim keeps i + 3*step < nbits
         while (i < lim) {
@@ -153,6 +153,7 @@ struct TileShared {
     unsigned long long tile;
     uint32_t range;
     uint32_t nact;
+    uint32_t sqb, sqe;  // isqrt(tile base), isqrt(tile end - 1), clamped to 32 bits
     uint32_t psoff[kMaxGroups];
     uint32_t red[1024 / 64];
     uint32_t chunk[64];
@@ -201,10 +202,15 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
                 // Primes p with p * p < tile end (Sec. 4: only primes up to
                 // the square root sieve anything); pidx over-counts by the
                 // few primes in the last 64-wide step, which mark nothing.
-                uint64_t s = (isqrt_dev(tend - 1) + 63) / 64;
+                const uint64_t se = isqrt_dev(tend - 1);
+                uint64_t s = (se + 63) / 64;
                 if (s >= a.pidx_len)
                     s = a.pidx_len - 1;
                 sh.nact = a.pidx[s];
+                const uint64_t Bt = d.base + k * kValsPerWord * pw;
+                const uint64_t sb = isqrt_dev(Bt);
+                sh.sqe = se > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)se;
+                sh.sqb = sb > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)sb;
             }
         }
         if (tid < 64)
@@ -268,6 +274,12 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
             // Every active prime is below 2^31 when the tile ends below 2^62.
             const bool narrow = tend <= (1ull << 62);
             const uint32_t b5 = (uint32_t)(B % 5);
+            const uint32_t sqb = sh.sqb, sqe = sh.sqe;
+            const uint64_t Bm1 = B - 1;
+            const uint32_t B32 = (uint32_t)B;
+            // Plane A_five is addressed as bits [32 pw, 32 pw + nbits) of one
+            // array that starts with A_one, so a mark needs no base add.
+            const uint32_t off5 = 32u * pw;
             for (uint32_t v = tid; v < n_work; v += NT) {
                 uint32_t kp, j, g;
                 if (v < n_items) {
@@ -281,27 +293,24 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
                     g = 1;
                 }
                 const PrimeConst pc = a.prm[kp];
-                const uint64_t P2 = (uint64_t)pc.p * pc.p;
-                const uint64_t M = P2 > B ? P2 : B;
-                if (M >= tend)
-                    continue;
+                if (pc.p > sqe)
+                    continue;  // P * P >= tile end: nothing to mark
                 uint32_t id1, id5;
-                const uint32_t R = pc.r & 0x1FFFFFFFu, inv5 = pc.r >> 29;
-                const uint32_t rem = start_rem(pc, B, P2, narrow);
-                wheel_start(pc.p, R, B, M, rem, id1, id5);
+                tile_start(pc, sqb, Bm1, B32, narrow, id1, id5);
                 const uint32_t step = g * pc.p;
                 const uint32_t off = j * pc.p;
                 if (a.skip5) {
                     // hit n of this lane has cofactor m0 + 6(j + n g) = c + n g (mod 5);
                     // it is a multiple of 5 when n = -c / g (mod 5)
+                    const uint32_t inv5 = pc.r >> 29;
                     const uint32_t ginv = inv_mod5(g);
                     const uint32_t c1 = (cofactor_mod5(b5, id1, 1, inv5) + j) % 5u;
                     const uint32_t c5 = (cofactor_mod5(b5, id5, 0, inv5) + j) % 5u;
-                    mark_plane_skip5(0, (uint64_t)id1 + off, step, nbits, ((5u - c1) * ginv) % 5u);
-                    mark_plane_skip5(base5, (uint64_t)id5 + off, step, nbits, ((5u - c5) * ginv) % 5u);
+                    mark_plane_skip5(0, id1 + off, step, nbits, ((5u - c1) * ginv) % 5u);
+                    mark_plane_skip5(0, id5 + off + off5, step, nbits + off5, ((5u - c5) * ginv) % 5u);
                 } else {
-                    mark_plane(0, (uint64_t)id1 + off, step, nbits);
-                    mark_plane(base5, (uint64_t)id5 + off, step, nbits);
+                    mark_plane(0, id1 + off, step, nbits);
+                    mark_plane(0, id5 + off + off5, step, nbits + off5);
                 }
             }
             // Bucket entries of this tile: one mark each.

@@ -73,6 +73,7 @@ struct sieve_ctx {
     uint32_t k_large = 0;  // first prime index the bucket sieve takes (multi-tile ranges)
     std::vector<double> inv_prefix;  // inv_prefix[k] = sum of 1/p over the first k primes
     uint64_t bucket_fallbacks = 0;   // jobs re-run with the exact bucket layout
+    uint64_t bucket_budget = 0;      // bucket entries one job may hold (larger jobs run in pieces)
 
     // Presieve tables.
     sieve::rt::DevBuf<uint2> d_pstab;

@@ -57,9 +57,11 @@ constexpr uint64_t kTable1_id5_p5 = table1_row(kT5p5);
 struct PrimeConst {
     uint32_t p;       // the prime, >= 5
     uint32_t r;       // bits 0..28: floor(p / 6); bits 29..31: p^-1 mod 5 (0 for p = 5)
-    uint32_t m_lo;    // floor((2^64 - 1) / p), low and high halves
-    uint32_t m_hi;
+    uint32_t m_lo;    // m = floor((2^64 - 1) / p), low and high halves; m < 2^62, so
+    uint32_t m_hi;    // bit 31 of m_hi is free and flags p = 5 (mod 6)
 };
+
+constexpr uint32_t kP5Flag = 0x80000000u;
 
 // x^-1 mod 5 for x mod 5 in 1..4 (0 stays 0).
 __host__ __device__ inline uint32_t inv_mod5(uint32_t x)
@@ -70,7 +72,13 @@ __host__ __device__ inline uint32_t inv_mod5(uint32_t x)
 inline PrimeConst make_prime_const(uint32_t p)
 {
     const uint64_t m = UINT64_MAX / p;
-    return PrimeConst{p, (p / 6u) | (inv_mod5(p) << 29), (uint32_t)m, (uint32_t)(m >> 32)};
+    return PrimeConst{p, (p / 6u) | (inv_mod5(p) << 29), (uint32_t)m,
+                      (uint32_t)(m >> 32) | (p % 6u == 5u ? kP5Flag : 0u)};
+}
+
+__host__ __device__ inline uint64_t prime_recip(const PrimeConst &pc)
+{
+    return ((uint64_t)(pc.m_hi & ~kP5Flag) << 32) | pc.m_lo;
 }
 
 __host__ __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b)
@@ -101,7 +109,23 @@ __host__ __device__ inline uint32_t start_rem(const PrimeConst &pc, uint64_t B, 
 {
     if (P2 > B)
         return pc.p - 1u;  // (P^2 - 1) mod P
-    return mod_invariant(B - 1, pc.p, ((uint64_t)pc.m_hi << 32) | pc.m_lo, narrow);
+    return mod_invariant(B - 1, pc.p, prime_recip(pc), narrow);
+}
+
+// Table 1 lookup: given dp = (Q - B) + 6(R + 1) (Q the greatest multiple of
+// P below the first value, 1 <= dp < 2^32), the start indices of P in both
+// planes.  p5: P = 5 (mod 6).
+__host__ __device__ inline void table1_ids(uint32_t dp, uint32_t R, bool p5, uint32_t &id1, uint32_t &id5)
+{
+    const uint32_t i0 = dp / 6u;       // = idx0 + R + 1
+    const uint32_t q = dp - 6u * i0;   // = Q mod 6
+    const uint64_t t1 = p5 ? kTable1_id1_p5 : kTable1_id1_p1;
+    const uint64_t t5 = p5 ? kTable1_id5_p5 : kTable1_id5_p1;
+    const uint32_t e1 = (uint32_t)(t1 >> (8u * q));
+    const uint32_t e5 = (uint32_t)(t5 >> (8u * q));
+    // id = idx0 + k*R + c = i0 + (k - 1)*R + c - 1
+    id1 = i0 + (e1 & 7u) * R + ((e1 >> 3) & 7u) - 1u;
+    id5 = i0 + (e5 & 7u) * R + ((e5 >> 3) & 7u) - 1u;
 }
 
 // Start indices (relative to base B) of prime P in both planes for a first
@@ -114,16 +138,47 @@ __host__ __device__ inline void wheel_start(uint32_t P, uint32_t R, uint64_t B, 
     const uint64_t x = M - 1;  // Q = x - rem, the greatest multiple of P below M
     // dp = (Q - B) + 6(R + 1), computed mod 2^32 (its true value is in [1, 2^32)).
     const uint32_t dp = (uint32_t)(x - B) - rem + 6u * (R + 1u);
-    const uint32_t i0 = dp / 6u;       // = idx0 + R + 1
-    const uint32_t q = dp - 6u * i0;   // = Q mod 6
-    const bool p5 = (P - 6u * R) == 5u;
-    const uint64_t t1 = p5 ? kTable1_id1_p5 : kTable1_id1_p1;
-    const uint64_t t5 = p5 ? kTable1_id5_p5 : kTable1_id5_p1;
-    const uint32_t e1 = (uint32_t)(t1 >> (8u * q));
-    const uint32_t e5 = (uint32_t)(t5 >> (8u * q));
-    // id = idx0 + k*R + c = i0 + (k - 1)*R + c - 1
-    id1 = i0 + (e1 & 7u) * R + ((e1 >> 3) & 7u) - 1u;
-    id5 = i0 + (e5 & 7u) * R + ((e5 >> 3) & 7u) - 1u;
+    table1_ids(dp, R, (P - 6u * R) == 5u, id1, id5);
+}
+
+// x mod P for x < 2^62 and P < 2^31 (the narrow case of mod_invariant),
+// where only the low 32 bits of the quotient estimate are formed: the
+// remainder x - q P is below 2P < 2^32, so it is determined mod 2^32.  With
+// x = xh 2^32 + xl and m = mh 2^32 + ml the high half of x m is
+// xh mh + hi(xl mh + hi(xl ml)) + hi(xh ml + lo(xl mh + hi(xl ml))) plus no
+// further carry into bit 64, and its low 32 bits need only 32-bit adds.
+__device__ inline uint32_t mod_narrow(uint32_t xl, uint32_t xh, uint32_t P, uint32_t ml, uint32_t mh)
+{
+    const uint32_t t = __umulhi(xl, ml);
+    const uint64_t u = (uint64_t)xl * mh + t;
+    const uint64_t w = (uint64_t)xh * ml + (uint32_t)u;
+    const uint32_t q = xh * mh + (uint32_t)(u >> 32) + (uint32_t)(w >> 32);
+    const uint32_t r = xl - q * P;
+    const uint32_t r2 = r - P;
+    return r2 < r ? r2 : r;  // r in [0, 2P): subtract P once when r >= P
+}
+
+// The same for the sieve kernel's tiles, with the square test done on 32-bit
+// per-tile thresholds: sqb = isqrt(B).  For P <= sqb the first value is
+// M = B, so x - B = -1 and dp = 6R + 5 - rem with rem = (B - 1) mod P, where
+// 6R + 5 is P + 4 or P for P = 1 or 5 (mod 6).  For P > sqb (the square lies
+// in the tile) M = P*P, rem = P - 1 and dp = P*P - B + 6 - (P mod 6), whose
+// true value is below 2^22 + 6, so 32-bit wrap-around arithmetic gives it.
+__device__ inline void tile_start(const PrimeConst &pc, uint32_t sqb, uint64_t Bm1, uint32_t B32, bool narrow,
+                                  uint32_t &id1, uint32_t &id5)
+{
+    const uint32_t R = pc.r & 0x1FFFFFFFu;
+    const bool p5 = (pc.m_hi & kP5Flag) != 0;
+    uint32_t dp;
+    if (pc.p > sqb) {
+        dp = pc.p * pc.p - B32 + (p5 ? 1u : 5u);
+    } else {
+        const uint32_t rem = narrow ? mod_narrow((uint32_t)Bm1, (uint32_t)(Bm1 >> 32), pc.p, pc.m_lo,
+                                                 pc.m_hi & ~kP5Flag)
+                                    : mod_invariant(Bm1, pc.p, prime_recip(pc), false);
+        dp = pc.p + (p5 ? 0u : 4u) - rem;
+    }
+    table1_ids(dp, R, p5, id1, id5);
 }
 
 }  // namespace sieve
