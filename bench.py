@@ -353,6 +353,7 @@ def main() -> int:
             "achieved": round(achieved, 1), "peak": round(LDS_PEAK_GBS, 1), "unit": "GB/s",
             "frac": round(achieved / LDS_PEAK_GBS, 4),
             "traffic": (tr["fetch_bytes"] + tr["write_bytes"]) if tr else None,
+            "valu_busy": round(tr["valu_busy"], 4) if tr and "valu_busy" in tr else None,
             "kernel": "k_sieve", "kernel_ms": round(k_ms, 4), "marks": marks,
             "algorithmic_bytes": lds_bytes}
 

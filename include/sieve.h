@@ -88,9 +88,15 @@ typedef struct sieve_ctx sieve_ctx;
  *                    exercises the overflow re-run (tests).
  *   cofactor_skip    where marks whose cofactor is a multiple of 5 are
  *                    skipped (such values are already cleared by the 5 of the
- *                    presieve): 0 (default) in the bucket sieve only;
- *                    SIEVE_SKIP_ALL also in the per-tile marking loop;
+ *                    presieve): 0 (default) or SIEVE_SKIP_SPLIT in the
+ *                    bucket sieve and for the primes whose tile work is
+ *                    split over several lanes (the small ones, many hits);
+ *                    SIEVE_SKIP_ALL in the whole per-tile marking loop too;
  *                    SIEVE_SKIP_NONE nowhere.  Needs presieve_groups >= 1.
+ *   dense_hits       primes with at least this many hits per plane per tile
+ *                    (default 512) are split over a multiple of 32 lanes, so
+ *                    that each lane's hits share one bit position and need
+ *                    one add each; SIEVE_DENSE_NEVER disables it.
  *   bucket_mem_mb    device memory one job may use for bucket entries, in
  *                    MiB (default 4096).  A job whose estimate is larger runs
  *                    as a sequence of jobs over tile-aligned pieces of its
@@ -107,6 +113,8 @@ typedef struct sieve_params {
     uint32_t bucket_slices;
     uint32_t cofactor_skip;
     uint32_t bucket_mem_mb;
+    uint32_t dense_hits;
+    uint32_t reserved[5];
 } sieve_params;
 
 #define SIEVE_PRESIEVE_NONE 0xFFFFFFFFu
@@ -115,6 +123,8 @@ typedef struct sieve_params {
 #define SIEVE_BUCKET_TINY 2u
 #define SIEVE_SKIP_ALL 1u
 #define SIEVE_SKIP_NONE 2u
+#define SIEVE_SKIP_SPLIT 3u
+#define SIEVE_DENSE_NEVER 0xFFFFFFFFu
 
 /* Fills *p with the library defaults for gfx950. */
 int sieve_default_params(sieve_params *p);

@@ -42,6 +42,8 @@ BUCKET_EXACT = 1
 BUCKET_TINY = 2
 SKIP_ALL = 1
 SKIP_NONE = 2
+SKIP_SPLIT = 3
+DENSE_NEVER = 0xFFFFFFFF
 
 _u64 = ctypes.c_uint64
 _p = ctypes.c_void_p
@@ -53,10 +55,11 @@ class Params(ctypes.Structure):
                 ("presieve_groups", ctypes.c_uint32), ("split_hits", ctypes.c_uint32),
                 ("bucket_threshold", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32),
                 ("use_graph", ctypes.c_uint32), ("bucket_slices", ctypes.c_uint32),
-                ("cofactor_skip", ctypes.c_uint32), ("bucket_mem_mb", ctypes.c_uint32)]
+                ("cofactor_skip", ctypes.c_uint32), ("bucket_mem_mb", ctypes.c_uint32),
+                ("dense_hits", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 5)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class ServerParams(ctypes.Structure):

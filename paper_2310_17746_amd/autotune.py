@@ -31,7 +31,7 @@ _SEGS = [(32768, 512, 4), (49152, 512, 3), (53248, 512, 3), (77824, 512, 2), (15
 GRIDS = {
     "count": [dict(segment_bytes=sg, block_threads=nt, wg_per_cu=w, split_hits=sp)
               for sg, nt, w in _SEGS for sp in (32, 64)],
-    "batch": [dict(segment_bytes=sg, block_threads=nt, wg_per_cu=w, split_hits=32, bucket_threshold=bt)
+    "batch": [dict(segment_bytes=sg, block_threads=nt, wg_per_cu=w, split_hits=64, bucket_threshold=bt)
               for sg, nt, w in _SEGS[1:4] for bt in (0, 8 * sg, 32 * sg)],
 }
 

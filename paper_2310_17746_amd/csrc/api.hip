@@ -94,7 +94,7 @@ void fill_defaults(sieve_params &p)
 {
     // Defaults from the sweep on MI355X (pi(10^11) count): 52 KiB tiles (three
     // fill the 160 KiB of LDS), 512 threads and three workgroups per CU
-    // (24 waves), work items of ~32 hits.
+    // (24 waves), work items of ~64 hits.
     if (!p.segment_bytes)
         p.segment_bytes = 52 * 1024;
     if (!p.block_threads)
@@ -102,11 +102,13 @@ void fill_defaults(sieve_params &p)
     if (!p.presieve_groups)
         p.presieve_groups = kMaxGroups;
     if (!p.split_hits)
-        p.split_hits = 32;
+        p.split_hits = 64;
     if (!p.wg_per_cu)
         p.wg_per_cu = std::max<uint32_t>(1, std::min<uint32_t>(4, (160 * 1024) / p.segment_bytes));
     if (!p.bucket_mem_mb)
         p.bucket_mem_mb = 4096;
+    if (!p.dense_hits)
+        p.dense_hits = 512;
 }
 
 int validate_params(const sieve_params &p, uint32_t lds_max)
@@ -122,7 +124,7 @@ int validate_params(const sieve_params &p, uint32_t lds_max)
         return SIEVE_E_INVAL;
     if (p.wg_per_cu < 1 || p.wg_per_cu > 16)
         return SIEVE_E_INVAL;
-    if (p.bucket_slices > SIEVE_BUCKET_TINY || p.cofactor_skip > SIEVE_SKIP_NONE)
+    if (p.bucket_slices > SIEVE_BUCKET_TINY || p.cofactor_skip > SIEVE_SKIP_SPLIT)
         return SIEVE_E_INVAL;
     return SIEVE_OK;
 }
@@ -207,14 +209,25 @@ int install_primes(sieve_ctx *c, uint64_t limit)
     const uint64_t plane_bits = (uint64_t)(c->prm.segment_bytes / 8) * 32;
     std::vector<uint2> items;
     std::vector<uint32_t> prefix(1, 0);
-    uint32_t ks = fm;
+    // A prime with at least dense_hits hits per plane is split over a
+    // multiple of 32 lanes: a lane's hits are then 32k P bits = kP words
+    // apart and share one bit position (fixed-mask marking).
+    uint32_t ks = fm, kd = fm;
     while (ks < n) {
-        uint64_t g = plane_bits / ((uint64_t)P[ks] * c->prm.split_hits);
-        if (g <= 1)
-            break;
-        g = std::min<uint64_t>(g, 0xFFFF);
-        if (g % 5 == 0)
-            --g;  // a lane's cofactors then run through every residue mod 5
+        const uint64_t hits = plane_bits / P[ks];
+        uint64_t g;
+        if (c->prm.dense_hits != SIEVE_DENSE_NEVER && hits >= c->prm.dense_hits && kd == ks) {
+            g = 32 * std::max<uint64_t>(1, hits / (32ull * c->prm.split_hits));
+            g = std::min<uint64_t>(g, 0xFFE0);
+            kd = ks + 1;
+        } else {
+            g = plane_bits / ((uint64_t)P[ks] * c->prm.split_hits);
+            if (g <= 1)
+                break;
+            g = std::min<uint64_t>(g, 0xFFFF);
+            if (g % 5 == 0)
+                --g;  // a lane's cofactors then run through every residue mod 5
+        }
         for (uint32_t j = 0; j < g; ++j)
             items.push_back(make_uint2(ks, (j << 16) | (uint32_t)g));
         prefix.push_back((uint32_t)items.size());
@@ -249,6 +262,7 @@ int install_primes(sieve_ctx *c, uint64_t limit)
     c->limit = limit;
     c->first_mark = fm;
     c->k_split = ks;
+    c->k_dense = kd;
     c->gen++;  // kernel arguments changed: a captured graph is stale
     return SIEVE_OK;
 }
@@ -513,6 +527,7 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed)
     a.nprimes = (uint32_t)c->h_primes.size();
     a.first_mark = c->first_mark;
     a.k_split = c->k_split;
+    a.k_dense = c->k_dense;
     a.items = c->d_items.p;
     a.item_prefix = c->d_item_prefix.p;
     a.ps_tab = c->d_pstab.p;
@@ -522,7 +537,8 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed)
     a.restore1 = c->restore1;
     a.restore5 = c->restore5;
     a.pw = pw;
-    a.skip5 = (c->ngroups >= 1 && c->prm.cofactor_skip == SIEVE_SKIP_ALL) ? 1u : 0u;
+    a.skip5 = c->ngroups < 1 || c->prm.cofactor_skip == SIEVE_SKIP_NONE ? 0u
+              : c->prm.cofactor_skip == SIEVE_SKIP_ALL ? 1u : 2u;
     a.bitmap = c->d_bitmap.p;
     a.chunk_counts = c->d_chunk_counts.p;
     a.chunk_range = c->d_chunk_range.p;

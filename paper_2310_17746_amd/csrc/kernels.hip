@@ -101,6 +101,32 @@ __device__ __forceinline__ void mark_plane(uint32_t base, uint32_t start, uint32
         lds_or(((i >> 3) & ~3u) + base, 1u << (i & 31));
 }
 
+// As mark_plane for a step that is a multiple of 32 bits: every hit then
+// sits at the same bit of its word, so the mask is fixed and the LDS byte
+// address advances by step / 8.  One add per mark.
+__device__ __forceinline__ void mark_plane_fixed(uint32_t start, uint32_t step, uint32_t nbits)
+{
+    if (start >= nbits)
+        return;
+    const uint32_t mask = 1u << (start & 31);
+    const uint32_t end = nbits >> 3;  // nbits is a whole number of words
+    const uint32_t sb = step >> 3;
+    uint32_t a = (start >> 3) & ~3u;
+    if (sb < (end >> 2)) {
+        const uint32_t lim = end - 3 * sb;  // a < lim keeps a + 3*sb < end
+        while (a < lim) {
+            asm volatile("" : "+v"(a));
+            lds_or(a, mask);
+            lds_or(a + sb, mask);
+            lds_or(a + 2 * sb, mask);
+            lds_or(a + 3 * sb, mask);
+            a += 4 * sb;
+        }
+    }
+    for (; a < end; a += sb)
+        lds_or(a, mask);
+}
+
 // As mark_plane, for a lane whose hits n = 0, 1, 2, ... have cofactors
 // running through the residues mod 5 with period 5, skipping hit n when
 // n = s (mod 5): those values are multiples of 5, already cleared by the
@@ -269,6 +295,8 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
             const uint32_t n_act = sh.nact < d.kbig ? sh.nact : d.kbig;
             const uint32_t ks = n_act < a.k_split ? n_act : a.k_split;
             const uint32_t n_items = ks > a.first_mark ? a.item_prefix[ks - a.first_mark] : 0;
+            const uint32_t kd = n_act < a.k_dense ? n_act : a.k_dense;
+            const uint32_t n_dense = kd > a.first_mark ? a.item_prefix[kd - a.first_mark] : 0;
             const uint32_t n_rest = n_act > a.k_split ? n_act - a.k_split : 0;
             const uint32_t n_work = n_items + n_rest;
             // Every active prime is below 2^31 when the tile ends below 2^62.
@@ -299,7 +327,11 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
                 tile_start(pc, sqb, Bm1, B32, narrow, id1, id5);
                 const uint32_t step = g * pc.p;
                 const uint32_t off = j * pc.p;
-                if (a.skip5) {
+                if (v < n_dense) {
+                    // g is a multiple of 32: fixed-mask marking
+                    mark_plane_fixed(id1 + off, step, nbits);
+                    mark_plane_fixed(id5 + off + off5, step, nbits + off5);
+                } else if (a.skip5 == 1 || (a.skip5 == 2 && v < n_items)) {
                     // hit n of this lane has cofactor m0 + 6(j + n g) = c + n g (mod 5);
                     // it is a multiple of 5 when n = -c / g (mod 5)
                     const uint32_t inv5 = pc.r >> 29;

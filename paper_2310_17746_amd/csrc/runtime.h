@@ -69,7 +69,7 @@ struct sieve_ctx {
     sieve::rt::DevBuf<uint32_t> d_pidx;
     sieve::rt::DevBuf<uint2> d_items;
     sieve::rt::DevBuf<uint32_t> d_item_prefix;
-    uint32_t first_mark = 0, k_split = 0;
+    uint32_t first_mark = 0, k_split = 0, k_dense = 0;
     uint32_t k_large = 0;  // first prime index the bucket sieve takes (multi-tile ranges)
     std::vector<double> inv_prefix;  // inv_prefix[k] = sum of 1/p over the first k primes
     uint64_t bucket_fallbacks = 0;   // jobs re-run with the exact bucket layout

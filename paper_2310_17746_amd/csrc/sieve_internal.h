@@ -97,6 +97,7 @@ struct SieveArgs {
     uint32_t nprimes;
     uint32_t first_mark;          // first prime index marked in LDS (after the presieve)
     uint32_t k_split;             // primes [first_mark, k_split) are split into items
+    uint32_t k_dense;             // primes [first_mark, k_dense) split over a multiple of 32 lanes
     const uint2 *items;           // {prime index, (j << 16) | g}
     const uint32_t *item_prefix;  // items before prime first_mark + i
     const uint2 *ps_tab;
@@ -104,7 +105,7 @@ struct SieveArgs {
     uint32_t ngroups;
     uint32_t restore1, restore5;  // bits of the presieved primes in word 0 of a tile based at 0
     uint32_t pw;                  // plane words per tile
-    uint32_t skip5;               // 1: multiples of 5 are presieved, so no mark with 5 | cofactor
+    uint32_t skip5;               // marks with 5 | cofactor skipped (5 is presieved): 1 every item, 2 split items
     unsigned long long *bitmap;   // list scratch (u64 words)
     uint32_t *chunk_counts;       // per chunk prime count
     uint32_t *chunk_range;        // per chunk: index of its range

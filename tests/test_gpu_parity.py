@@ -198,6 +198,10 @@ def test_error_paths(sv):
     dict(segment_bytes=49152, bucket_threshold=pkg.BUCKET_NEVER),  # no bucket sieve
     dict(cofactor_skip=pkg.SKIP_ALL, split_hits=24),            # skip 5 | cofactor in tiles too
     dict(cofactor_skip=pkg.SKIP_NONE, bucket_threshold=70000, segment_bytes=16384),
+    dict(cofactor_skip=pkg.SKIP_SPLIT, split_hits=64),          # skip on split items only
+    dict(dense_hits=pkg.DENSE_NEVER),                           # no fixed-mask marking
+    dict(dense_hits=40, split_hits=8, segment_bytes=8192),      # fixed-mask marking for most primes
+    dict(dense_hits=2000, cofactor_skip=pkg.SKIP_ALL),          # fixed-mask beside the skip path
 ])
 def test_parameter_grid_parity(params):
     with pkg.Sieve(0, params) as s:
