@@ -155,6 +155,53 @@ def bench_list(pkg, torch, params, steps=5):
                                     "algorithmic_bytes": nbytes}}
 
 
+def bench_list_window(pkg, torch, params, steps=3):
+    """Config 3 window: sorted uint64 list of the primes in [10^12, 10^12 + 10^10)."""
+    lo, hi = 10 ** 12, 10 ** 12 + 10 ** 10
+    s = pkg.Sieve(0, params)
+    s.ensure_base_for(hi)
+    out = torch.empty(pkg.list_bound(lo, hi), dtype=torch.int64, device="cuda")
+    n = s.list(lo, hi, out=out, elem_bytes=8).numel()
+    torch.cuda.synchronize()
+    s.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.list(lo, hi, out=out, elem_bytes=8)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    sieve_ms, post_ms, jobs = s.timing()
+    s.close()
+    words = ((hi - lo + 5) // 6 + 31) // 32
+    post = post_ms / jobs
+    nbytes = 8 * n + 8 * words
+    gbs = nbytes / (post * 1e-3) / 1e9
+    return {"workload": "sorted uint64 list of the primes in [10^12, 10^12 + 10^10)", "primes": n,
+            "ms_per_call": round(dt * 1e3, 3), "primes_per_s": round(n / dt, 1),
+            "sieve_kernel_ms": round(sieve_ms / jobs, 4), "compaction_ms": round(post, 4),
+            "compaction_roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0,
+                                    "unit": "GB/s", "frac": round(gbs / 8000.0, 4),
+                                    "algorithmic_bytes": nbytes}}
+
+
+def bench_cold(pkg, torch, params, hi=10 ** 11 + 1):
+    """The headline count from a fresh context: creation, base primes, first count."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = pkg.Sieve(0, params)
+    t1 = time.perf_counter()
+    s.ensure_base_for(hi)
+    t2 = time.perf_counter()
+    c = s.count(2, hi)
+    t3 = time.perf_counter()
+    c2 = s.count(2, hi)
+    t4 = time.perf_counter()
+    s.close()
+    return {"workload": "count of [2, 10^11 + 1) from a fresh context", "count_ok": c == c2 == 4118054813,
+            "create_ms": round((t1 - t0) * 1e3, 3), "base_primes_ms": round((t2 - t1) * 1e3, 3),
+            "first_count_ms": round((t3 - t2) * 1e3, 3), "second_count_ms": round((t4 - t3) * 1e3, 3),
+            "cold_total_ms": round((t3 - t0) * 1e3, 3)}
+
+
 def bench_batch(pkg, torch, params, workloads, steps=3):
     """Config 4: 4096 seeded uneven ranges, half listed as uint64."""
     lo, hi, mode = workloads.batch_ranges(0)
@@ -366,7 +413,9 @@ def main() -> int:
         print("bench: autotune batch", file=sys.stderr, flush=True)
         tuned = autotune.tune("batch")
         bparams = dict(params, **tuned["params"])
-        for name, fn in (("list_1e9", lambda: bench_list(pkg, torch, params)),
+        for name, fn in (("cold", lambda: bench_cold(pkg, torch, params)),
+                         ("list_1e9", lambda: bench_list(pkg, torch, params)),
+                         ("list_window", lambda: bench_list_window(pkg, torch, params)),
                          ("batch_4096", lambda: bench_batch(pkg, torch, bparams, workloads)),
                          ("stream", lambda: bench_stream(pkg, torch, params)),
                          ("serve_2000", lambda: bench_serve(pkg, workloads))):
@@ -387,6 +436,13 @@ def main() -> int:
         cpu = {"value": round((hi - a) / (t3 - t2), 1), "unit": "ints/s", "cores": th, "kind": "oracle",
                "sample": "oracle count of [%d, %d) (%d integers, the top of the workload): %d primes in %.2f s"
                          % (a, hi, hi - a, oc, t3 - t2)}
+        # the same oracle on one thread, over the top 10^9 integers of the workload
+        a1 = max(lo, hi - 10 ** 9)
+        t4 = time.perf_counter()
+        oracle.count(a1, hi, threads=1)
+        t5 = time.perf_counter()
+        cpu["one_thread"] = {"value": round((hi - a1) / (t5 - t4), 1), "unit": "ints/s",
+                             "sample": "oracle count of [%d, %d) on 1 thread" % (a1, hi)}
 
     line = {
         "metric": "sieved integers/s at pi(1e11) count",

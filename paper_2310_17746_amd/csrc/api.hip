@@ -418,10 +418,10 @@ int ensure_capacity(sieve_ctx *c, uint64_t nranges, uint64_t nchunks, uint64_t n
         c->cap_chunks = grow(c->cap_chunks, nchunks, 64);
         c->d_bitmap.release();
         c->d_chunk_counts.release();
-        c->d_chunk_range.release();
+        c->d_chunk_vbase.release();
         c->d_chunk_off.release();
         if (!c->d_bitmap.reserve(c->cap_chunks * kChunkWords) || !c->d_chunk_counts.reserve(c->cap_chunks) ||
-            !c->d_chunk_range.reserve(c->cap_chunks) || !c->d_chunk_off.reserve(c->cap_chunks))
+            !c->d_chunk_vbase.reserve(c->cap_chunks) || !c->d_chunk_off.reserve(c->cap_chunks))
             return SIEVE_E_NOMEM;
         changed = true;
     }
@@ -541,7 +541,6 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed)
               : c->prm.cofactor_skip == SIEVE_SKIP_ALL ? 1u : 2u;
     a.bitmap = c->d_bitmap.p;
     a.chunk_counts = c->d_chunk_counts.p;
-    a.chunk_range = c->d_chunk_range.p;
     a.bdata = c->d_bdata.p;
     a.boff = c->d_boff.p;
     a.bcount = c->d_bcount.p;
@@ -560,13 +559,12 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed)
     f.status = c->d_status.p;
     f.chunk_counts = c->d_chunk_counts.p;
     f.chunk_off = c->d_chunk_off.p;
+    f.chunk_vbase = c->d_chunk_vbase.p;
     if ((e = launch_finalize(f, kFinalizeGrid, s)) != hipSuccess)
         return e;
     CompactArgs k;
     k.job = job;
-    k.ranges = ranges;
-    k.chunk_range = c->d_chunk_range.p;
-    k.status = c->d_status.p;
+    k.chunk_vbase = c->d_chunk_vbase.p;
     k.bitmap = c->d_bitmap.p;
     k.chunk_off = c->d_chunk_off.p;
     if ((e = launch_compact(k, (uint32_t)c->cus * 4, s)) != hipSuccess)
@@ -898,7 +896,7 @@ void destroy_ctx(sieve_ctx *c)
     c->d_status.release();
     c->d_bitmap.release();
     c->d_chunk_counts.release();
-    c->d_chunk_range.release();
+    c->d_chunk_vbase.release();
     c->d_chunk_off.release();
     if (c->h_blob)
         (void)hipHostFree(c->h_blob);

@@ -185,8 +185,10 @@ struct TileShared {
     uint32_t chunk[64];
 };
 
+// Three 512-thread workgroups per CU (24 waves, 6 per SIMD) need at most 80
+// VGPRs; the attribute holds the compiler to that.
 template <int NT>
-__global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) k_sieve(SieveArgs a)
 {
     extern __shared__ uint32_t lds[];
     const uint32_t tid = threadIdx.x;
@@ -417,10 +419,8 @@ __global__ void __launch_bounds__(NT) k_sieve(SieveArgs a)
             __syncthreads();
             const uint32_t nch = nw_pad / kChunkWords;
             const uint64_t cbase = d.chunk0 + k * (pw / kChunkWords);
-            if (tid < nch) {
+            if (tid < nch)
                 a.chunk_counts[cbase + tid] = sh.chunk[tid];
-                a.chunk_range[cbase + tid] = rix;
-            }
         } else {
             cnt = wave_sum(cnt);
             if (lane == 0)
@@ -705,16 +705,21 @@ __global__ void __launch_bounds__(kFinalizeThreads) k_finalize(FinalizeArgs a)
                 woff += q < wave ? s_w[q] : 0u;
                 btot += s_w[q];
             }
-            if (i < d.nchunks)
+            if (i < d.nchunks) {
                 a.chunk_off[d.chunk0 + i] = d.out_off + sp + s_carry + woff + incl - c;
+                // chunk i of the range covers kChunkVals values from base + i kChunkVals
+                a.chunk_vbase[d.chunk0 + i] = d.base + (uint64_t)kChunkVals * i;
+            }
             __syncthreads();
             if (tid == 0)
                 s_carry += btot;
             __syncthreads();
         }
+        __shared__ uint32_t s_over;
         if (tid == 0) {
             const unsigned long long total = s_carry + sp;
             a.counts[r] = total;
+            s_over = total > d.cap ? 1u : 0u;
             if (total > d.cap) {
                 a.status[r] = -3;  // SIEVE_E_CAPACITY
             } else {
@@ -736,6 +741,10 @@ __global__ void __launch_bounds__(kFinalizeThreads) k_finalize(FinalizeArgs a)
             }
         }
         __syncthreads();
+        if (s_over)  // the compaction writes nothing for a range that does not fit
+            for (uint32_t i = tid; i < d.nchunks; i += kFinalizeThreads)
+                a.chunk_off[d.chunk0 + i] = ~0ull;
+        __syncthreads();
     }
 }
 
@@ -752,12 +761,42 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(CompactArgs a)
         return;
     const uint64_t nchunks = a.job->nchunks;
 
-    for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-        const uint32_t r = a.chunk_range[c];  // written by the sieve kernel
-        if (a.status[r] != 0)
-            continue;  // over capacity: nothing is written for this range
-        const RangeDesc &d = a.ranges[r];
-        uint64_t m = a.bitmap[c * kChunkWords + tid];
+    // The loads of chunk c + gridDim.x (bitmap word, output offset, value
+    // base: independent of each other) are issued before chunk c is
+    // expanded, so that their latency overlaps the current chunk's work.
+    // vz is a zero the compiler cannot see as uniform, which keeps the
+    // per-chunk loads on the vector memory path (in-order completion).
+    uint32_t vz;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(vz));
+    // The output pointer, uniform and in the global address space, so that
+    // the stores are global (not flat) stores.
+    // (readfirstlane returns a signed int: each half goes through uint32_t so
+    // that widening never sign-extends.)
+    const uint64_t op = (uint64_t)(size_t)a.job->out;
+    const uint32_t op_hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(op >> 32));
+    const uint32_t op_lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)op);
+    const uint64_t opu = ((uint64_t)op_hi << 32) | op_lo;
+    __attribute__((address_space(1))) T *const out = (__attribute__((address_space(1))) T *)(size_t)opu;
+    uint64_t c = blockIdx.x;
+    uint64_t m = 0, coff = ~0ull, vb0 = 0;
+    if (c < nchunks) {
+        m = a.bitmap[c * kChunkWords + tid];
+        coff = a.chunk_off[c + vz];
+        vb0 = a.chunk_vbase[c + vz];
+    }
+    asm volatile("" : "+v"(m), "+v"(coff), "+v"(vb0));
+    for (; c < nchunks; c += gridDim.x) {
+        const uint64_t cn = c + gridDim.x;
+        uint64_t mn = 0, coffn = ~0ull, vbn = 0;
+        if (cn < nchunks) {
+            mn = a.bitmap[cn * kChunkWords + tid];
+            coffn = a.chunk_off[cn + vz];
+            vbn = a.chunk_vbase[cn + vz];
+        }
+        if (coff == ~0ull) {  // its range is over capacity: nothing is written
+            m = mn, coff = coffn, vb0 = vbn;
+            continue;
+        }
         const uint32_t cnt = __popcll(m);
         const uint32_t incl = wave_incl_scan(cnt, lane);
         if (lane == kWave - 1)
@@ -769,10 +808,9 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(CompactArgs a)
             wmax = s_wt[q] > wmax ? s_wt[q] : wmax;
         }
         const uint32_t wtot = s_wt[wave];
-        const uint64_t obase = a.chunk_off[c] + woff;
-        const uint64_t vb = d.base + kChunkVals * (c - d.chunk0) + kValsPerWord * tid;
+        const uint64_t obase = coff + woff;
+        const uint64_t vb = vb0 + kValsPerWord * tid;
         const uint32_t excl = incl - cnt;
-        T *out = (T *)a.job->out;
         // Passes over rank windows of kStagePerWave, uniform across the block.
         for (uint32_t pass = 0; pass < wmax; pass += kStagePerWave) {
             if (excl < pass + kStagePerWave && excl + cnt > pass) {
@@ -795,6 +833,7 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(CompactArgs a)
             __syncthreads();
         }
         __syncthreads();
+        m = mn, coff = coffn, vb0 = vbn;
     }
 }
 

@@ -88,7 +88,7 @@ struct sieve_ctx {
     sieve::rt::DevBuf<int32_t> d_status;
     sieve::rt::DevBuf<unsigned long long> d_bitmap;
     sieve::rt::DevBuf<uint32_t> d_chunk_counts;
-    sieve::rt::DevBuf<uint32_t> d_chunk_range;
+    sieve::rt::DevBuf<unsigned long long> d_chunk_vbase;
     sieve::rt::DevBuf<unsigned long long> d_chunk_off;
     unsigned char *h_blob = nullptr;  // pinned staging for the blob
     size_t h_blob_n = 0;

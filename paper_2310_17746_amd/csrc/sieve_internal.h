@@ -108,7 +108,6 @@ struct SieveArgs {
     uint32_t skip5;               // marks with 5 | cofactor skipped (5 is presieved): 1 every item, 2 split items
     unsigned long long *bitmap;   // list scratch (u64 words)
     uint32_t *chunk_counts;       // per chunk prime count
-    uint32_t *chunk_range;        // per chunk: index of its range
     const uint32_t *bdata;        // bucket entries: bit | plane << 31
     const unsigned long long *boff;  // exact layout, per tile: first entry
     const uint32_t *bcount;       // exact layout, per tile: entries
@@ -147,15 +146,15 @@ struct FinalizeArgs {
     int32_t *status;
     const uint32_t *chunk_counts;
     unsigned long long *chunk_off;
+    unsigned long long *chunk_vbase;  // per chunk: value base of its first word
 };
 
 struct CompactArgs {
     const JobHeader *job;
-    const RangeDesc *ranges;
-    const uint32_t *chunk_range;  // per chunk: index of its range
-    const int32_t *status;
+    const unsigned long long *chunk_vbase;  // per chunk: value base of its first word
     const unsigned long long *bitmap;
-    const unsigned long long *chunk_off;
+    const unsigned long long *chunk_off;    // per chunk: first output element; ~0 when
+                                            // its range does not fit (nothing is written)
 };
 
 }  // namespace sieve

@@ -245,3 +245,22 @@ def test_bucket_sieve_long_ranges_at_1e15(thr, slices):
             if mode[i]:
                 assert np.array_equal(host[int(off[i]):int(off[i]) + len(want)], want), (thr, i)
         assert s.count(int(lo[0]), int(hi[0])) == int(counts[0])
+
+
+@pytest.mark.parametrize("elem_bytes", [4, 8])
+def test_list_output_at_address_with_bit31_set(sv, elem_bytes):
+    """Output pointers whose low 32 bits are >= 2^31 (the kernels carry the
+    output address in two 32-bit halves; neither half may be sign-extended)."""
+    lo, hi = 10 ** 9, 10 ** 9 + 3 * 10 ** 6
+    cap = pkg.list_bound(lo, hi)
+    n_el = (1 << 31) // elem_bytes + cap + 1024
+    big = torch.empty(n_el, dtype=torch.int32 if elem_bytes == 4 else torch.int64, device="cuda")
+    base = big.data_ptr()
+    # first element index whose address has bit 31 set in its low word
+    k = 0
+    while ((base + k * elem_bytes) & 0x80000000) == 0:
+        k += (1 << 20) // elem_bytes
+    assert k + cap <= n_el
+    got = _u(sv.list(lo, hi, out=big[k:k + cap], elem_bytes=elem_bytes), elem_bytes).astype(np.uint64)
+    assert np.array_equal(got, oracle.primes(lo, hi))
+    del big
