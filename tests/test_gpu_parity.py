@@ -108,6 +108,12 @@ def test_pi_1e10_and_1e11_counts(sv, pi_tab):
     assert sv.count(2, 10 ** 11 + 1) == pi_tab[10 ** 11]
 
 
+def test_pi_1e12_count(sv, pi_tab):
+    # base primes to 10^6; the bucket sieve takes the primes above four plane lengths
+    sv.ensure_base_for(10 ** 12 + 1)
+    assert sv.count(2, 10 ** 12 + 1) == pi_tab[10 ** 12]
+
+
 def test_large_windows_vs_oracle(sv):
     for lo, n in [(10 ** 12, 3 * 10 ** 7), (10 ** 15 - 10 ** 7, 2 * 10 ** 7), (2 ** 50, 10 ** 6)]:
         hi = lo + n
