@@ -748,92 +748,103 @@ __global__ void __launch_bounds__(kFinalizeThreads) k_finalize(FinalizeArgs a)
     }
 }
 
+// Workgroup barrier for LDS hand-offs only: waits for this wave's LDS
+// operations, not for its global stores (a full __syncthreads also drains the
+// stores, which would serialise the compaction on write latency).
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kCompactThreads) k_compact(CompactArgs a)
 {
     constexpr uint32_t kW = kCompactThreads / kWave;
+    constexpr uint32_t kU = 4;  // contiguous chunks per workgroup iteration
     __shared__ T s_stage[kW][kStagePerWave];
     __shared__ uint32_t s_wt[kW];
+    __shared__ unsigned long long s_meta[2][kU];  // output offset, value base
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1);
     const uint32_t wave = tid / kWave;
     if (a.job->elem_bytes != (int32_t)sizeof(T))
         return;
     const uint64_t nchunks = a.job->nchunks;
-
-    // The loads of chunk c + gridDim.x (bitmap word, output offset, value
-    // base: independent of each other) are issued before chunk c is
-    // expanded, so that their latency overlaps the current chunk's work.
-    // vz is a zero the compiler cannot see as uniform, which keeps the
-    // per-chunk loads on the vector memory path (in-order completion).
-    uint32_t vz;
-    asm volatile("v_mov_b32 %0, 0" : "=v"(vz));
     // The output pointer, uniform and in the global address space, so that
-    // the stores are global (not flat) stores.
-    // (readfirstlane returns a signed int: each half goes through uint32_t so
-    // that widening never sign-extends.)
+    // the stores are global (not flat) stores.  (readfirstlane returns a
+    // signed int: each half goes through uint32_t so that widening never
+    // sign-extends.)
     const uint64_t op = (uint64_t)(size_t)a.job->out;
     const uint32_t op_hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(op >> 32));
     const uint32_t op_lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)op);
-    const uint64_t opu = ((uint64_t)op_hi << 32) | op_lo;
-    __attribute__((address_space(1))) T *const out = (__attribute__((address_space(1))) T *)(size_t)opu;
-    uint64_t c = blockIdx.x;
-    uint64_t m = 0, coff = ~0ull, vb0 = 0;
-    if (c < nchunks) {
-        m = a.bitmap[c * kChunkWords + tid];
-        coff = a.chunk_off[c + vz];
-        vb0 = a.chunk_vbase[c + vz];
-    }
-    asm volatile("" : "+v"(m), "+v"(coff), "+v"(vb0));
-    for (; c < nchunks; c += gridDim.x) {
-        const uint64_t cn = c + gridDim.x;
-        uint64_t mn = 0, coffn = ~0ull, vbn = 0;
-        if (cn < nchunks) {
-            mn = a.bitmap[cn * kChunkWords + tid];
-            coffn = a.chunk_off[cn + vz];
-            vbn = a.chunk_vbase[cn + vz];
+    __attribute__((address_space(1))) T *const out =
+        (__attribute__((address_space(1))) T *)(size_t)(((uint64_t)op_hi << 32) | op_lo);
+
+    // Each iteration takes kU contiguous chunks.  Their loads are issued
+    // together at the top; the stores of all kU chunks stay in flight until
+    // the next iteration's loads are waited for.
+    for (uint64_t c0 = (uint64_t)blockIdx.x * kU; c0 < nchunks; c0 += (uint64_t)gridDim.x * kU) {
+        uint64_t mu[kU];
+#pragma unroll
+        for (uint32_t u = 0; u < kU; ++u)
+            mu[u] = c0 + u < nchunks ? a.bitmap[(c0 + u) * kChunkWords + tid] : 0ull;
+        if (tid < kU) {
+            const uint64_t c = c0 + tid;
+            // ~0: past the end, or the range does not fit (nothing is written)
+            s_meta[0][tid] = c < nchunks ? a.chunk_off[c] : ~0ull;
+            s_meta[1][tid] = c < nchunks ? a.chunk_vbase[c] : 0ull;
         }
-        if (coff == ~0ull) {  // its range is over capacity: nothing is written
-            m = mn, coff = coffn, vb0 = vbn;
-            continue;
-        }
-        const uint32_t cnt = __popcll(m);
-        const uint32_t incl = wave_incl_scan(cnt, lane);
-        if (lane == kWave - 1)
-            s_wt[wave] = incl;
-        __syncthreads();
-        uint32_t woff = 0, wmax = 0;
-        for (uint32_t q = 0; q < kW; ++q) {
-            woff += q < wave ? s_wt[q] : 0u;
-            wmax = s_wt[q] > wmax ? s_wt[q] : wmax;
-        }
-        const uint32_t wtot = s_wt[wave];
-        const uint64_t obase = coff + woff;
-        const uint64_t vb = vb0 + kValsPerWord * tid;
-        const uint32_t excl = incl - cnt;
-        // Passes over rank windows of kStagePerWave, uniform across the block.
-        for (uint32_t pass = 0; pass < wmax; pass += kStagePerWave) {
-            if (excl < pass + kStagePerWave && excl + cnt > pass) {
-                uint64_t mm = m;
-                uint32_t pos = excl;
-                while (mm) {
-                    const uint32_t b = (uint32_t)__builtin_ctzll(mm);
-                    mm &= mm - 1;
-                    if (pos >= pass && pos < pass + kStagePerWave)
-                        s_stage[wave][pos - pass] = (T)(vb + 3ull * b + 1ull + (b & 1u));
-                    ++pos;
+        // Consume the bitmap words here, before any store of this iteration:
+        // the vector memory counter completes in order, so a later wait for
+        // them would also wait for this iteration's stores.
+#pragma unroll
+        for (uint32_t u = 0; u < kU; ++u)
+            asm volatile("" : "+v"(mu[u]));
+        lds_barrier();
+#pragma unroll
+        for (uint32_t u = 0; u < kU; ++u) {
+            const uint64_t coff = s_meta[0][u];
+            if (coff == ~0ull)
+                continue;  // the same for every thread of the block
+            const uint64_t m = mu[u];
+            const uint32_t cnt = __popcll(m);
+            const uint32_t incl = wave_incl_scan(cnt, lane);
+            if (lane == kWave - 1)
+                s_wt[wave] = incl;
+            lds_barrier();
+            uint32_t woff = 0, wmax = 0;
+            for (uint32_t q = 0; q < kW; ++q) {
+                woff += q < wave ? s_wt[q] : 0u;
+                wmax = s_wt[q] > wmax ? s_wt[q] : wmax;
+            }
+            const uint32_t wtot = s_wt[wave];
+            const uint64_t obase = coff + woff;
+            const uint64_t vb = s_meta[1][u] + kValsPerWord * tid;
+            const uint32_t excl = incl - cnt;
+            // Passes over rank windows of kStagePerWave, uniform across the block.
+            for (uint32_t pass = 0; pass < wmax; pass += kStagePerWave) {
+                if (excl < pass + kStagePerWave && excl + cnt > pass) {
+                    uint64_t mm = m;
+                    uint32_t pos = excl;
+                    while (mm) {
+                        const uint32_t b = (uint32_t)__builtin_ctzll(mm);
+                        mm &= mm - 1;
+                        if (pos >= pass && pos < pass + kStagePerWave)
+                            s_stage[wave][pos - pass] = (T)(vb + 3ull * b + 1ull + (b & 1u));
+                        ++pos;
+                    }
                 }
+                lds_barrier();
+                if (wtot > pass) {
+                    const uint32_t n_in = (wtot - pass) < kStagePerWave ? (wtot - pass) : kStagePerWave;
+                    for (uint32_t e = lane; e < n_in; e += kWave)
+                        out[obase + pass + e] = s_stage[wave][e];
+                }
+                lds_barrier();
             }
-            __syncthreads();
-            if (wtot > pass) {
-                const uint32_t n_in = (wtot - pass) < kStagePerWave ? (wtot - pass) : kStagePerWave;
-                for (uint32_t e = lane; e < n_in; e += kWave)
-                    out[obase + pass + e] = s_stage[wave][e];
-            }
-            __syncthreads();
+            lds_barrier();  // every wave has read s_wt before the next chunk rewrites it
         }
-        __syncthreads();
-        m = mn, coff = coffn, vb0 = vbn;
+        lds_barrier();  // s_meta is rewritten by the next iteration
     }
 }
 
