@@ -356,8 +356,8 @@ def main() -> int:
         return 0
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see the sharding design); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs on a single GPU and has no "
+              "multi-GPU path; run with --gpus 1", file=sys.stderr)
         return 2
 
     import torch
