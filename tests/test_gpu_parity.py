@@ -270,3 +270,21 @@ def test_list_output_at_address_with_bit31_set(sv, elem_bytes):
     got = _u(sv.list(lo, hi, out=big[k:k + cap], elem_bytes=elem_bytes), elem_bytes).astype(np.uint64)
     assert np.array_equal(got, oracle.primes(lo, hi))
     del big
+
+
+def test_top_of_domain_window():
+    """Tiles above 2^62 (the wide remainder path) up to hi = 2^63: every
+    wheel candidate of the window is classified by deterministic
+    Miller-Rabin (exact below 3.3e24), and counts agree with the list."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    hi = 1 << 63
+    lo = hi - (1 << 17)
+    with pkg.Sieve(0) as s:
+        s.ensure_base_for(hi)  # primes up to isqrt(2^63 - 1) = 3037000499
+        got = _u(s.list(lo, hi, elem_bytes=8), 8)
+        want = [n for n in range(lo | 1, hi, 2) if n % 3 and brute.is_prime_mr(n)]
+        assert np.array_equal(got, np.array(want, dtype=np.uint64))
+        mid = lo + (1 << 16) + 7
+        assert s.count(lo, mid) + s.count(mid, hi) == len(want)
+        assert s.count_batch([lo, mid], [mid, hi]).sum() == len(want)
