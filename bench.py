@@ -436,6 +436,25 @@ def main() -> int:
         cpu = {"value": round((hi - a) / (t3 - t2), 1), "unit": "ints/s", "cores": th, "kind": "oracle",
                "sample": "oracle count of [%d, %d) (%d integers, the top of the workload): %d primes in %.2f s"
                          % (a, hi, hi - a, oc, t3 - t2)}
+        # the oracle on the other workloads (context for the extras; bounded samples)
+        t6 = time.perf_counter()
+        n2 = len(oracle.primes(2, 10 ** 9 + 1, elem_bytes=4, threads=th))
+        t7 = time.perf_counter()
+        n3 = len(oracle.primes(10 ** 12, 10 ** 12 + 10 ** 9, elem_bytes=8, threads=th))
+        t8 = time.perf_counter()
+        from paper_2310_17746_amd import workloads as _wl
+        blo, bhi, _ = _wl.batch_ranges(0)
+        sel = np.random.default_rng(3).choice(len(blo), 64, replace=False)
+        bints = int((bhi[sel] - blo[sel]).sum())
+        for a_, b_ in zip(blo[sel].tolist(), bhi[sel].tolist()):
+            oracle.count(a_, b_, threads=th)
+        t9 = time.perf_counter()
+        cpu["other_workloads"] = {
+            "list_1e9": {"primes_per_s": round(n2 / (t7 - t6), 1), "ms": round((t7 - t6) * 1e3, 1)},
+            "list_window_sample": {"sample": "[10^12, 10^12 + 10^9)", "primes_per_s": round(n3 / (t8 - t7), 1),
+                                   "ms": round((t8 - t7) * 1e3, 1)},
+            "batch_sample": {"sample": "64 of the 4096 ranges, counted", "ints_per_s": round(bints / (t9 - t8), 1),
+                             "ms": round((t9 - t8) * 1e3, 1)}}
         # the same oracle on one thread, over the top 10^9 integers of the workload
         a1 = max(lo, hi - 10 ** 9)
         t4 = time.perf_counter()
