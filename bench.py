@@ -403,6 +403,17 @@ def main() -> int:
             "valu_busy": round(tr["valu_busy"], 4) if tr and "valu_busy" in tr else None,
             "kernel": "k_sieve", "kernel_ms": round(k_ms, 4), "marks": marks,
             "algorithmic_bytes": lds_bytes}
+    # Measured peak of the instruction the marks use (32-bit LDS OR), from the
+    # library's LDS probe in this run: conflict-free and random-word patterns.
+    probe = {}
+    for mode in ("or_linear", "or_random"):
+        ops, _ = pkg.probe_lds(mode, iters=2048, wg_per_cu=2)
+        probe[mode] = ops * 4 / 1e9  # GB/s of 4-byte read-modify-writes
+    roof["instr_peak"] = {"instruction": "ds_or_b32", "unit": "GB/s",
+                          "conflict_free": round(probe["or_linear"], 1),
+                          "frac_conflict_free": round(achieved / probe["or_linear"], 4),
+                          "random_words": round(probe["or_random"], 1),
+                          "frac_random_words": round(achieved / probe["or_random"], 4)}
 
     s.close()
     extras = None

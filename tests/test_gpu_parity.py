@@ -288,3 +288,14 @@ def test_top_of_domain_window():
         mid = lo + (1 << 16) + 7
         assert s.count(lo, mid) + s.count(mid, hi) == len(want)
         assert s.count_batch([lo, mid], [mid, hi]).sum() == len(want)
+
+
+def test_lds_probe_modes():
+    """The LDS probe runs every mode; a conflict-free pattern is at least as
+    fast as random words, and random words faster than one word per wave."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rates = {m: pkg.probe_lds(m, iters=256, wg_per_cu=2)[0] for m in pkg.PROBE_MODES}
+    assert all(r > 0 for r in rates.values())
+    assert rates["or_linear"] >= 0.9 * rates["or_random"]
+    assert rates["or_random"] > rates["or_same"]
