@@ -27,6 +27,7 @@ hipError_t launch_bucket(const BucketArgs &a, int pass, uint32_t grid, hipStream
 hipError_t launch_bucket_scan(const BucketScanArgs &a, hipStream_t s);
 hipError_t launch_sieve(const SieveArgs &a, uint32_t nt, uint32_t grid, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs &a, uint32_t grid, hipStream_t s);
+hipError_t launch_seg(const SegArgs &a, int pass, uint32_t grid, hipStream_t s);
 hipError_t launch_compact(const CompactArgs &a, uint32_t grid, hipStream_t s);
 }  // namespace sieve
 
@@ -285,7 +286,7 @@ void plan_range(uint64_t lo, uint64_t hi, uint32_t pw, uint64_t &ntiles, uint64_
 struct Plan {
     std::vector<RangeDesc> ranges;
     uint64_t nlist = 0;  // ranges in list mode
-    uint64_t ntiles = 0, nchunks = 0, nunits = 0;
+    uint64_t ntiles = 0, nchunks = 0, nunits = 0, nseg = 0;
     uint64_t best = 0;  // bucket entries of the estimated layout
 };
 
@@ -354,7 +355,14 @@ int make_plan(const sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t
             d.chunk0 = pl.nchunks;
             pl.nchunks += nch;
             pl.nlist++;
+            d.nseg = (uint32_t)((nch + kSegChunks - 1) / kSegChunks);
         }
+        // every range carries the running segment index, so that seg0 + nseg
+        // never decreases along the table (count ranges add no segment)
+        if (pl.nseg + d.nseg > 0xFFFFFFFFull)
+            return SIEVE_E_INVAL;
+        d.seg0 = (uint32_t)pl.nseg;
+        pl.nseg += d.nseg;
     }
     return SIEVE_OK;
 }
@@ -420,8 +428,12 @@ int ensure_capacity(sieve_ctx *c, uint64_t nranges, uint64_t nchunks, uint64_t n
         c->d_chunk_counts.release();
         c->d_chunk_vbase.release();
         c->d_chunk_off.release();
+        c->d_seg_sum.release();
+        c->d_seg_base.release();
+        // segments: at most one per chunk (every segment holds at least one)
         if (!c->d_bitmap.reserve(c->cap_chunks * kChunkWords) || !c->d_chunk_counts.reserve(c->cap_chunks) ||
-            !c->d_chunk_vbase.reserve(c->cap_chunks) || !c->d_chunk_off.reserve(c->cap_chunks))
+            !c->d_chunk_vbase.reserve(c->cap_chunks) || !c->d_chunk_off.reserve(c->cap_chunks) ||
+            !c->d_seg_sum.reserve(c->cap_chunks) || !c->d_seg_base.reserve(c->cap_chunks))
             return SIEVE_E_NOMEM;
         changed = true;
     }
@@ -552,15 +564,26 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed)
         return e;
     if (timed && (e = hipEventRecord(c->ev[1], s)) != hipSuccess)
         return e;
+    SegArgs g;
+    g.job = job;
+    g.ranges = ranges;
+    g.chunk_counts = c->d_chunk_counts.p;
+    g.seg_sum = c->d_seg_sum.p;
+    g.seg_base = c->d_seg_base.p;
+    g.chunk_off = c->d_chunk_off.p;
+    g.chunk_vbase = c->d_chunk_vbase.p;
+    if ((e = launch_seg(g, 0, (uint32_t)c->cus * 2, s)) != hipSuccess)
+        return e;
     FinalizeArgs f;
     f.job = job;
     f.ranges = ranges;
     f.counts = c->d_counts.p;
     f.status = c->d_status.p;
-    f.chunk_counts = c->d_chunk_counts.p;
-    f.chunk_off = c->d_chunk_off.p;
-    f.chunk_vbase = c->d_chunk_vbase.p;
+    f.seg_sum = c->d_seg_sum.p;
+    f.seg_base = c->d_seg_base.p;
     if ((e = launch_finalize(f, kFinalizeGrid, s)) != hipSuccess)
+        return e;
+    if ((e = launch_seg(g, 1, (uint32_t)c->cus * 2, s)) != hipSuccess)
         return e;
     CompactArgs k;
     k.job = job;
@@ -636,6 +659,7 @@ int run_job_once(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *h
     h->ntiles = pl.ntiles;
     h->nchunks = pl.nchunks;
     h->nunits = pl.nunits;
+    h->nseg = pl.nseg;
     h->bmode = 1;
     h->nranges = (uint32_t)n;
     h->nlist = (uint32_t)nlist;
@@ -898,6 +922,8 @@ void destroy_ctx(sieve_ctx *c)
     c->d_chunk_counts.release();
     c->d_chunk_vbase.release();
     c->d_chunk_off.release();
+    c->d_seg_sum.release();
+    c->d_seg_base.release();
     if (c->h_blob)
         (void)hipHostFree(c->h_blob);
     if (c->h_counts)

@@ -668,10 +668,63 @@ __global__ void __launch_bounds__(kFinalizeThreads) k_bucket_scan(BucketScanArgs
         a.boff[n] = s_carry;
 }
 
+// Range of scan segment `sg`: the first range whose segments end after it
+// (count ranges hold no segment and never satisfy the test first).
+__device__ inline uint32_t seg_range(const RangeDesc *ranges, uint32_t nranges, uint64_t sg)
+{
+    uint32_t lo = 0, hi = nranges;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if ((uint64_t)ranges[mid].seg0 + ranges[mid].nseg > sg)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+// Sum of the chunk counts of every scan segment (4 chunks per thread).
+__global__ void __launch_bounds__(kFinalizeThreads) k_seg_sum(SegArgs a)
+{
+    __shared__ unsigned long long s_w[kFinalizeThreads / kWave];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & (kWave - 1);
+    const uint32_t wave = tid / kWave;
+    const uint64_t nseg = a.job->nseg;
+    const uint32_t nranges = a.job->nranges;
+    for (uint64_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
+        const RangeDesc &d = a.ranges[seg_range(a.ranges, nranges, sg)];
+        const uint64_t c0 = d.chunk0 + (sg - d.seg0) * kSegChunks;
+        const uint64_t c1 = d.chunk0 + d.nchunks;
+        unsigned long long v = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < kSegChunks / kFinalizeThreads; ++q) {
+            const uint64_t c = c0 + q * kFinalizeThreads + tid;
+            v += c < c1 ? a.chunk_counts[c] : 0u;
+        }
+        for (int o = kWave / 2; o > 0; o >>= 1)
+            v += __shfl_xor(v, o);
+        if (lane == 0)
+            s_w[wave] = v;
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long t = 0;
+            for (uint32_t q = 0; q < kFinalizeThreads / kWave; ++q)
+                t += s_w[q];
+            a.seg_sum[sg] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// Per range: the primes 2 and 3, the count and capacity status, and for list
+// ranges the output base of each scan segment (an exclusive scan of the
+// segment sums; ~0 for every segment of a range that does not fit).
 __global__ void __launch_bounds__(kFinalizeThreads) k_finalize(FinalizeArgs a)
 {
-    __shared__ uint32_t s_w[kFinalizeThreads / kWave];
+    __shared__ unsigned long long s_w[kFinalizeThreads / kWave];
     __shared__ unsigned long long s_carry;
+    __shared__ uint32_t s_over;
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1);
     const uint32_t wave = tid / kWave;
@@ -693,29 +746,31 @@ __global__ void __launch_bounds__(kFinalizeThreads) k_finalize(FinalizeArgs a)
         if (tid == 0)
             s_carry = 0;
         __syncthreads();
-        for (uint32_t b0 = 0; b0 < d.nchunks; b0 += kFinalizeThreads) {
+        for (uint32_t b0 = 0; b0 < d.nseg; b0 += kFinalizeThreads) {
             const uint32_t i = b0 + tid;
-            const uint32_t c = i < d.nchunks ? a.chunk_counts[d.chunk0 + i] : 0u;
-            const uint32_t incl = wave_incl_scan(c, lane);
+            const unsigned long long v = i < d.nseg ? a.seg_sum[d.seg0 + i] : 0ull;
+            // inclusive wave scan (64-bit)
+            unsigned long long incl = v;
+            for (uint32_t o = 1; o < kWave; o <<= 1) {
+                const unsigned long long t = __shfl_up(incl, o);
+                if (lane >= o)
+                    incl += t;
+            }
             if (lane == kWave - 1)
                 s_w[wave] = incl;
             __syncthreads();
-            uint32_t woff = 0, btot = 0;
+            unsigned long long woff = 0, btot = 0;
             for (uint32_t q = 0; q < kFinalizeThreads / kWave; ++q) {
-                woff += q < wave ? s_w[q] : 0u;
+                woff += q < wave ? s_w[q] : 0ull;
                 btot += s_w[q];
             }
-            if (i < d.nchunks) {
-                a.chunk_off[d.chunk0 + i] = d.out_off + sp + s_carry + woff + incl - c;
-                // chunk i of the range covers kChunkVals values from base + i kChunkVals
-                a.chunk_vbase[d.chunk0 + i] = d.base + (uint64_t)kChunkVals * i;
-            }
+            if (i < d.nseg)
+                a.seg_base[d.seg0 + i] = d.out_off + sp + s_carry + woff + incl - v;
             __syncthreads();
             if (tid == 0)
                 s_carry += btot;
             __syncthreads();
         }
-        __shared__ uint32_t s_over;
         if (tid == 0) {
             const unsigned long long total = s_carry + sp;
             a.counts[r] = total;
@@ -742,8 +797,54 @@ __global__ void __launch_bounds__(kFinalizeThreads) k_finalize(FinalizeArgs a)
         }
         __syncthreads();
         if (s_over)  // the compaction writes nothing for a range that does not fit
-            for (uint32_t i = tid; i < d.nchunks; i += kFinalizeThreads)
-                a.chunk_off[d.chunk0 + i] = ~0ull;
+            for (uint32_t i = tid; i < d.nseg; i += kFinalizeThreads)
+                a.seg_base[d.seg0 + i] = ~0ull;
+        __syncthreads();
+    }
+}
+
+// Output offset and value base of every chunk: the segment's base plus an
+// exclusive scan of the chunk counts inside the segment (4 per thread).
+__global__ void __launch_bounds__(kFinalizeThreads) k_seg_scan(SegArgs a)
+{
+    constexpr uint32_t kQ = kSegChunks / kFinalizeThreads;
+    __shared__ uint32_t s_w[kFinalizeThreads / kWave];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & (kWave - 1);
+    const uint32_t wave = tid / kWave;
+    const uint64_t nseg = a.job->nseg;
+    const uint32_t nranges = a.job->nranges;
+    for (uint64_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
+        const RangeDesc &d = a.ranges[seg_range(a.ranges, nranges, sg)];
+        const uint64_t base = a.seg_base[sg];
+        const uint64_t cs = d.chunk0 + (sg - d.seg0) * kSegChunks;  // segment's first chunk
+        const uint64_t c1 = d.chunk0 + d.nchunks;
+        const uint64_t cf = cs + (uint64_t)tid * kQ;  // this thread's first chunk
+        uint32_t cnt[kQ];
+        uint32_t tsum = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < kQ; ++q) {
+            cnt[q] = cf + q < c1 ? a.chunk_counts[cf + q] : 0u;
+            tsum += cnt[q];
+        }
+        const uint32_t incl = wave_incl_scan(tsum, lane);
+        if (lane == kWave - 1)
+            s_w[wave] = incl;
+        __syncthreads();
+        uint32_t woff = 0;
+        for (uint32_t q = 0; q < kFinalizeThreads / kWave; ++q)
+            woff += q < wave ? s_w[q] : 0u;
+        uint64_t run = woff + incl - tsum;  // primes before this thread's first chunk
+#pragma unroll
+        for (uint32_t q = 0; q < kQ; ++q) {
+            const uint64_t c = cf + q;
+            if (c < c1) {
+                a.chunk_off[c] = base == ~0ull ? ~0ull : base + run;
+                // chunk i of the range covers kChunkVals values from base + i kChunkVals
+                a.chunk_vbase[c] = d.base + (uint64_t)kChunkVals * (c - d.chunk0);
+            }
+            run += cnt[q];
+        }
         __syncthreads();
     }
 }
@@ -924,6 +1025,15 @@ hipError_t launch_sieve(const SieveArgs &a, uint32_t nt, uint32_t grid, hipStrea
 hipError_t launch_finalize(const FinalizeArgs &a, uint32_t grid, hipStream_t s)
 {
     hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(kFinalizeThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg(const SegArgs &a, int pass, uint32_t grid, hipStream_t s)
+{
+    if (pass == 0)
+        hipLaunchKernelGGL(k_seg_sum, dim3(grid), dim3(kFinalizeThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_seg_scan, dim3(grid), dim3(kFinalizeThreads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -90,6 +90,7 @@ struct sieve_ctx {
     sieve::rt::DevBuf<uint32_t> d_chunk_counts;
     sieve::rt::DevBuf<unsigned long long> d_chunk_vbase;
     sieve::rt::DevBuf<unsigned long long> d_chunk_off;
+    sieve::rt::DevBuf<unsigned long long> d_seg_sum, d_seg_base;  // chunk-offset scan segments
     unsigned char *h_blob = nullptr;  // pinned staging for the blob
     size_t h_blob_n = 0;
     unsigned long long *h_counts = nullptr;  // pinned

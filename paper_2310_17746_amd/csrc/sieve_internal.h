@@ -29,6 +29,7 @@ constexpr int kMaxGroups = 5;                               // presieve pattern 
 constexpr uint32_t kCompactThreads = 512;                   // one bitmap word per thread
 constexpr uint32_t kStagePerWave = 512;                     // compaction staging entries per wave
 constexpr uint32_t kFinalizeThreads = 1024;
+constexpr uint32_t kSegChunks = 4096;  // chunks per scan segment (4 per thread of 1024)
 constexpr uint32_t kBucketThreads = 256;    // primes per bucket work unit
 constexpr uint32_t kBucketWindow = 2048;    // tiles per bucket work unit (LDS bins)
 constexpr uint32_t kBucketMinPrimes = 32768; // fewest large primes worth a bucket pass
@@ -52,6 +53,8 @@ struct RangeDesc {
     uint32_t bwins;      // tile windows of kBucketWindow tiles
     uint64_t bbase;      // estimated layout: first entry of this range's buckets
     uint32_t bcap;       // estimated layout: entries reserved per tile
+    uint32_t nseg;       // list ranges: scan segments of kSegChunks chunks
+    uint32_t seg0;       // global index of the first segment (running count)
     uint32_t pad;
 };
 
@@ -68,6 +71,7 @@ struct JobHeader {
     void *out;           // caller's output buffer (list ranges)
     int32_t elem_bytes;  // 4 or 8
     int32_t pad;
+    uint64_t nseg;       // scan segments over all list ranges
 };
 
 // Counters zeroed at the start of every job.
@@ -144,7 +148,21 @@ struct FinalizeArgs {
     const RangeDesc *ranges;
     unsigned long long *counts;
     int32_t *status;
+    const unsigned long long *seg_sum;  // per segment: primes in its chunks
+    unsigned long long *seg_base;       // per segment: first output element; ~0 when
+                                        // its range does not fit
+};
+
+// Chunk-offset scan of the list ranges in segments, spread over workgroups:
+// k_seg_sum adds each segment's chunk counts, k_finalize scans the segment
+// sums of each range, k_seg_scan writes every chunk's output offset and value
+// base from its segment's base.
+struct SegArgs {
+    const JobHeader *job;
+    const RangeDesc *ranges;
     const uint32_t *chunk_counts;
+    unsigned long long *seg_sum;
+    const unsigned long long *seg_base;
     unsigned long long *chunk_off;
     unsigned long long *chunk_vbase;  // per chunk: value base of its first word
 };
