@@ -64,21 +64,23 @@ typedef struct sieve_ctx sieve_ctx;
  * size, range and segment bytes).  Zero in any field selects the default.
  *   segment_bytes    LDS bytes per tile for the two bit planes together;
  *                    a multiple of 4096 in [8192, 159744] (156 KiB, leaving
- *                    room for the kernel's static LDS in 160 KiB).  A tile
+ *                    room for the kernel's static LDS in 160 KiB); default
+ *                    53248 (52 KiB: three tiles per compute unit).  A tile
  *                    covers 24 * segment_bytes consecutive integers.
- *   block_threads    threads per workgroup: 256, 512 or 1024.
+ *   block_threads    threads per workgroup: 256, 512 or 1024 (default 512).
  *   presieve_groups  number of repeating-pattern groups used to initialise
  *                    the planes (0..5; 5 covers every prime 5..61).  0 means
  *                    default; SIEVE_PRESIEVE_NONE disables the presieve.
- *   split_hits       target hits per marking work item: primes with more
- *                    hits per tile are split over several lanes.
+ *   split_hits       target hits per marking work item (default 64): primes
+ *                    with more hits per tile are split over several lanes.
  *   bucket_threshold primes at least this large go through the bucket
  *                    sieve on ranges of two or more tiles.  0 (default):
  *                    four plane lengths (16 * segment_bytes), and only on
  *                    ranges with at least 32768 such primes; any other
  *                    value applies to every multi-tile range;
  *                    SIEVE_BUCKET_NEVER disables the bucket sieve.
- *   wg_per_cu        persistent workgroups launched per compute unit.
+ *   wg_per_cu        persistent workgroups launched per compute unit
+ *                    (default: as many tiles as fit in 160 KiB, at most 4).
  *   use_graph        1: batched calls replay a captured hipGraph.
  *   bucket_slices    bucket storage layout: 0 (default) sizes each tile's
  *                    slice from the expected hit count plus a wide margin

@@ -3,9 +3,11 @@
 // Owns the context: the resident base primes (the paper's Sieve Data Store,
 // Sec. 4) with their per-prime constants, the presieve pattern tables, the
 // marking work items, grow-only device scratch, pinned staging, a stream and
-// a captured graph.  Every count / list / batch call is planned here (ranges
+// captured graphs.  Every count / list / batch call is planned here (ranges
 // cut into tiles of 192 * PW integers, Sec. 2.2) and executed as one job:
-// zero -> sieve (persistent) -> finalize -> compact.
+// zero -> [bucket fill] -> sieve (persistent) -> segment sums -> finalize ->
+// segment scan -> compact; a job whose bucket entries would exceed the
+// budget runs as a sequence of jobs over tile-aligned pieces.
 #include <stdlib.h>
 #include <string.h>
 

@@ -1,12 +1,20 @@
 // Device kernels of the segmented wheel sieve (gfx950, wave64).
 //
+// k_zero       clears the job's counters, counts and bucket cursors (a kernel,
+//              so that the whole job can be captured in a graph).
+// k_bucket     bucket sieve for the large primes of multi-tile ranges: walks
+//              each prime's hits tile by tile and bins them per tile (count,
+//              scan and fill passes for the exact layout; one fill pass into
+//              estimated per-tile slices otherwise).
 // k_sieve      one persistent launch over every tile of a job.  Per tile, in
 //              LDS: presieve init, Table 1 starts + marking of the remaining
-//              base primes, edge masks, then either a popcount into the
-//              range's count or a value-ordered bitmap + per-chunk counts.
-// k_finalize   per range: adds 2 and 3 when in range; for list ranges an
-//              exclusive scan of the chunk counts gives each chunk's output
-//              offset, and the capacity check sets the range status.
+//              base primes, the tile's bucket entries, edge masks, then either
+//              a popcount into the range's count or a value-ordered bitmap +
+//              per-chunk counts.
+// k_seg_sum    per scan segment (4096 chunks of a list range): chunk-count sum.
+// k_finalize   per range: adds 2 and 3 when in range, scans the segment sums
+//              of list ranges into segment output bases, sets count and status.
+// k_seg_scan   per scan segment: each chunk's output offset and value base.
 // k_compact    per bitmap chunk: popcount, block prefix, LDS staging and
 //              coalesced stores of the primes as uint32 or uint64.
 #include "sieve_internal.h"
