@@ -25,7 +25,7 @@ namespace sieve {
 hipError_t set_sieve_lds_limit(uint32_t bytes);
 hipError_t launch_zero(const JobHeader *job, unsigned long long *counters, unsigned long long *counts,
                        uint32_t *bcount, hipStream_t s);
-hipError_t launch_bucket(const BucketArgs &a, int pass, uint32_t grid, hipStream_t s);
+hipError_t launch_bucket(const BucketArgs &a, int pass, uint32_t cus, hipStream_t s);
 hipError_t launch_bucket_scan(const BucketScanArgs &a, hipStream_t s);
 hipError_t launch_sieve(const SieveArgs &a, uint32_t nt, uint32_t grid, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs &a, uint32_t grid, hipStream_t s);
@@ -290,6 +290,7 @@ struct Plan {
     uint64_t nlist = 0;  // ranges in list mode
     uint64_t ntiles = 0, nchunks = 0, nunits = 0, nseg = 0;
     uint64_t best = 0;  // bucket entries of the estimated layout
+    uint32_t bwin = 0;  // most tiles in one bucket window
 };
 
 int make_plan(const sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, const uint8_t *mode,
@@ -334,6 +335,7 @@ int make_plan(const sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t
         d.bunit0 = pl.nunits;
         pl.nunits += d.bunits;
         if (d.bunits) {
+            pl.bwin = std::max(pl.bwin, (uint32_t)std::min<uint64_t>(nt, kBucketWindow));
             // Expected entries per tile: each large prime p hits a plane of
             // nbits bits nbits/p times on average; reserve that plus a
             // margin of 8 standard deviations (the count is a sum of nearly
@@ -500,7 +502,8 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed)
     b.nbits = 32 * pw;
     b.span = 192ull * pw;
     b.span_rcp = UINT64_MAX / b.span;
-    const uint32_t bgrid = (uint32_t)c->cus * 8;
+    b.win = c->bucket_win ? c->bucket_win : kBucketWindow;
+    const uint32_t bcus = (uint32_t)c->cus;
     if (phase != kPhaseRest) {
         if (timed && phase == kPhaseBucketCount && (e = hipEventRecord(c->ev[3], s)) != hipSuccess)
             return e;
@@ -510,7 +513,7 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed)
             return e;
     }
     if (phase == kPhaseBucketCount) {
-        if ((e = launch_bucket(b, 0, bgrid, s)) != hipSuccess)
+        if ((e = launch_bucket(b, 0, bcus, s)) != hipSuccess)
             return e;
         BucketScanArgs sc;
         sc.job = job;
@@ -526,7 +529,7 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed)
     if (phase == kPhaseRest || phase == kPhaseDirect) {
         if (timed && (e = hipEventRecord(c->ev[5], s)) != hipSuccess)
             return e;
-        if ((e = launch_bucket(b, phase == kPhaseRest ? 1 : 2, bgrid, s)) != hipSuccess)
+        if ((e = launch_bucket(b, phase == kPhaseRest ? 1 : 2, bcus, s)) != hipSuccess)
             return e;
     }
     SieveArgs a;
@@ -674,6 +677,18 @@ int run_job_once(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *h
     if (e != hipSuccess)
         return hip_status(e);
     const bool buckets = pl.nunits != 0;
+    if (buckets) {
+        // LDS bins for the largest window of the job, in power-of-two steps
+        // so that captured graphs (which hold the size) are seldom re-made
+        uint32_t w = 64;
+        while (w < pl.bwin)
+            w <<= 1;
+        w = std::min(w, kBucketWindow);
+        if (w != c->bucket_win) {
+            c->bucket_win = w;
+            c->gen++;
+        }
+    }
     // Results back to the host: per-range counts and status, and the flags.
     auto finish = [&]() -> hipError_t {
         hipError_t f = hipSuccess;

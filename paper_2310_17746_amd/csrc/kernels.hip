@@ -17,6 +17,8 @@
 // k_seg_scan   per scan segment: each chunk's output offset and value base.
 // k_compact    per bitmap chunk: popcount, block prefix, LDS staging and
 //              coalesced stores of the primes as uint32 or uint64.
+#include <atomic>
+
 #include "sieve_internal.h"
 #include "wheel.h"
 
@@ -527,9 +529,17 @@ __device__ inline HitWalk walk_init(const BucketArgs &a, const RangeDesc &d, uin
     return w;
 }
 
-__device__ inline uint32_t find_unit_range(const RangeDesc *ranges, uint32_t nranges, uint64_t u)
+// Range of unit u: the last range whose first unit is <= u.  Searches from
+// range r0, which must satisfy ranges[r0].bunit0 <= u: exponential steps,
+// then bisection of the bracket.
+__device__ inline uint32_t find_unit_range(const RangeDesc *ranges, uint32_t nranges, uint32_t r0, uint64_t u)
 {
-    uint32_t lo = 0, hi = nranges;
+    uint32_t lo = r0, step = 1;
+    while (lo + step < nranges && ranges[lo + step].bunit0 <= u) {
+        lo += step;
+        step <<= 1;
+    }
+    uint32_t hi = lo + step < nranges ? lo + step : nranges;
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
         if (ranges[mid].bunit0 <= u)
@@ -542,19 +552,27 @@ __device__ inline uint32_t find_unit_range(const RangeDesc *ranges, uint32_t nra
 
 }  // namespace
 
+// LDS (dynamic, a.win bins): fill passes hold the 64-bit slice base of
+// every tile of the window, then the per-tile counts, which the fill walk
+// reuses as slot cursors.
 template <int PASS>
 __global__ void __launch_bounds__(kBucketThreads) k_bucket(BucketArgs a)
 {
-    __shared__ uint32_t s_cnt[kBucketWindow];
-    __shared__ uint32_t s_cur[PASS ? kBucketWindow : 1];
-    __shared__ unsigned long long s_base[PASS ? kBucketWindow : 1];
+    extern __shared__ unsigned long long s_bucket[];
+    unsigned long long *s_base = s_bucket;
+    uint32_t *s_cnt = (uint32_t *)(s_bucket + (PASS ? a.win : 0));
     const uint32_t tid = threadIdx.x;
     const uint64_t nunits = a.job->nunits;
     const uint32_t nranges = a.job->nranges;
     const uint32_t nbits = a.nbits;
 
+    uint32_t r = 0;
+    uint64_t r_end = 0;  // one past the last unit of range r
     for (uint64_t u = blockIdx.x; u < nunits; u += gridDim.x) {
-        const uint32_t r = find_unit_range(a.ranges, nranges, u);
+        if (u >= r_end) {
+            r = find_unit_range(a.ranges, nranges, r, u);
+            r_end = a.ranges[r].bunit0 + a.ranges[r].bunits;
+        }
         const RangeDesc &d = a.ranges[r];
         // unit = (prime block, tile window) of range r
         const uint32_t ur = (uint32_t)(u - d.bunit0);
@@ -563,11 +581,8 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket(BucketArgs a)
         const uint32_t wend = (d.ntiles - w0) < kBucketWindow ? d.ntiles : w0 + kBucketWindow;
         const uint32_t k = d.kbig + blk * kBucketThreads + tid;
         HitWalk w = walk_init(a, d, k, w0, wend);
-        for (uint32_t i = tid; i < wend - w0; i += kBucketThreads) {
+        for (uint32_t i = tid; i < wend - w0; i += kBucketThreads)
             s_cnt[i] = 0;
-            if (PASS)
-                s_cur[i] = 0;
-        }
         __syncthreads();
         if (PASS == 0) {
             while (w.t1 < wend) {
@@ -601,6 +616,7 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket(BucketArgs a)
             __syncthreads();
             for (uint32_t i = tid; i < wend - w0; i += kBucketThreads) {
                 const uint32_t n = s_cnt[i];
+                s_cnt[i] = 0;  // now the slot cursor of tile i
                 if (n) {
                     const uint64_t g = d.tile0 + w0 + i;
                     const uint32_t at = atomicAdd(&a.bcursor[g], n);
@@ -617,7 +633,7 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket(BucketArgs a)
             __syncthreads();
             while (w.t1 < wend) {
                 if (w.c1) {
-                    const uint32_t slot = atomicAdd(&s_cur[w.t1 - w0], 1u);
+                    const uint32_t slot = atomicAdd(&s_cnt[w.t1 - w0], 1u);
                     const unsigned long long b0 = s_base[w.t1 - w0];
                     if (b0 != ~0ull)
                         a.bdata[b0 + slot] = w.b1;
@@ -626,7 +642,7 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket(BucketArgs a)
             }
             while (w.t5 < wend) {
                 if (w.c5) {
-                    const uint32_t slot = atomicAdd(&s_cur[w.t5 - w0], 1u);
+                    const uint32_t slot = atomicAdd(&s_cnt[w.t5 - w0], 1u);
                     const unsigned long long b0 = s_base[w.t5 - w0];
                     if (b0 != ~0ull)
                         a.bdata[b0 + slot] = w.b5 | 0x80000000u;
@@ -994,14 +1010,46 @@ hipError_t launch_zero(const JobHeader *job, unsigned long long *counters, unsig
     return hipGetLastError();
 }
 
-hipError_t launch_bucket(const BucketArgs &a, int pass, uint32_t grid, hipStream_t s)
+namespace {
+
+// Workgroups of one bucket pass resident per CU for a given LDS size (the
+// grid is exactly the resident set: the kernel strides over its units).
+template <int PASS>
+int bucket_residency(size_t lds)
 {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bucket<PASS>, kBucketThreads, lds) != hipSuccess ||
+        nb < 1) {
+        (void)hipGetLastError();
+        nb = 1;
+    }
+    return nb;
+}
+
+}  // namespace
+
+hipError_t launch_bucket(const BucketArgs &a, int pass, uint32_t cus, hipStream_t s)
+{
+    if (a.win < 1 || a.win > kBucketWindow || (a.win & (a.win - 1)))
+        return hipErrorInvalidValue;
+    const size_t lds = (size_t)a.win * (pass ? sizeof(unsigned long long) + sizeof(uint32_t) : sizeof(uint32_t));
+    // residency per (pass, power-of-two window): queried once
+    static std::atomic<int> occ[3][16];
+    int w2 = 0;
+    while ((1u << w2) < a.win)
+        ++w2;
+    int nb = occ[pass][w2].load(std::memory_order_relaxed);
+    if (nb == 0) {
+        nb = pass == 0 ? bucket_residency<0>(lds) : pass == 1 ? bucket_residency<1>(lds) : bucket_residency<2>(lds);
+        occ[pass][w2].store(nb, std::memory_order_relaxed);
+    }
+    const dim3 grid(cus * (uint32_t)nb);
     if (pass == 0)
-        hipLaunchKernelGGL(k_bucket<0>, dim3(grid), dim3(kBucketThreads), 0, s, a);
+        hipLaunchKernelGGL(k_bucket<0>, grid, dim3(kBucketThreads), lds, s, a);
     else if (pass == 1)
-        hipLaunchKernelGGL(k_bucket<1>, dim3(grid), dim3(kBucketThreads), 0, s, a);
+        hipLaunchKernelGGL(k_bucket<1>, grid, dim3(kBucketThreads), lds, s, a);
     else
-        hipLaunchKernelGGL(k_bucket<2>, dim3(grid), dim3(kBucketThreads), 0, s, a);
+        hipLaunchKernelGGL(k_bucket<2>, grid, dim3(kBucketThreads), lds, s, a);
     return hipGetLastError();
 }
 

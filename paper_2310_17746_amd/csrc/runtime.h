@@ -74,6 +74,7 @@ struct sieve_ctx {
     std::vector<double> inv_prefix;  // inv_prefix[k] = sum of 1/p over the first k primes
     uint64_t bucket_fallbacks = 0;   // jobs re-run with the exact bucket layout
     uint64_t bucket_budget = 0;      // bucket entries one job may hold (larger jobs run in pieces)
+    uint32_t bucket_win = 0;         // per-tile LDS bins of the bucket kernels (kernel argument)
 
     // Presieve tables.
     sieve::rt::DevBuf<uint2> d_pstab;

@@ -134,6 +134,8 @@ struct BucketArgs {
     uint32_t nbits;               // bits per plane per tile (32 * pw)
     uint64_t span;                // integers per tile (192 * pw)
     uint64_t span_rcp;            // floor((2^64 - 1) / span)
+    uint32_t win;                 // LDS bins per workgroup: >= the tiles of every unit's window
+    uint32_t pad;
 };
 
 struct BucketScanArgs {
