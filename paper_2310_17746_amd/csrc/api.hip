@@ -374,14 +374,15 @@ int make_plan(const sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct BlobLayout {
-    size_t ranges, total;
+    size_t ranges, visit, total;
 };
 
 BlobLayout blob_layout(uint64_t nranges)
 {
     BlobLayout L;
     L.ranges = align_up(sizeof(JobHeader), 256);
-    L.total = align_up(L.ranges + sizeof(RangeDesc) * std::max<uint64_t>(nranges, 1), 256);
+    L.visit = align_up(L.ranges + sizeof(RangeDesc) * std::max<uint64_t>(nranges, 1), 256);
+    L.total = align_up(L.visit + sizeof(VisitEntry) * std::max<uint64_t>(nranges, 1), 256);
     return L;
 }
 
@@ -536,6 +537,7 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed)
     memset(&a, 0, sizeof a);
     a.job = job;
     a.ranges = ranges;
+    a.visit = (const VisitEntry *)(c->d_blob.p + L.visit);
     a.counters = c->d_counters.p;
     a.counts = c->d_counts.p;
     a.prm = c->d_prm.p;
@@ -670,10 +672,30 @@ int run_job_once(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *h
     h->nlist = (uint32_t)nlist;
     h->out = out;
     h->elem_bytes = elem_bytes;
-    if (n)
+    if (n) {
         memcpy(c->h_blob + L.ranges, pl.ranges.data(), n * sizeof(RangeDesc));
+        // Visit order: most Table 1 starts per tile first (kbig is the
+        // number of primes a tile of the range starts in the tile), ties in
+        // storage order.
+        std::vector<uint32_t> ord(n);
+        for (uint64_t i = 0; i < n; ++i)
+            ord[i] = (uint32_t)i;
+        std::stable_sort(ord.begin(), ord.end(),
+                         [&](uint32_t x, uint32_t y) { return pl.ranges[x].kbig > pl.ranges[y].kbig; });
+        VisitEntry *v = (VisitEntry *)(c->h_blob + L.visit);
+        uint64_t pos = 0;
+        for (uint64_t j = 0; j < n; ++j) {
+            v[j].vstart = pos;
+            v[j].range = ord[j];
+            v[j].pad = 0;
+            pos += pl.ranges[ord[j]].ntiles;
+        }
+    }
     hipError_t e = hipMemcpyAsync(c->d_blob.p, c->h_blob, L.ranges + n * sizeof(RangeDesc),
                                   hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && n)
+        e = hipMemcpyAsync(c->d_blob.p + L.visit, c->h_blob + L.visit, n * sizeof(VisitEntry),
+                           hipMemcpyHostToDevice, s);
     if (e != hipSuccess)
         return hip_status(e);
     const bool buckets = pl.nunits != 0;

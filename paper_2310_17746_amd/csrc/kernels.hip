@@ -223,18 +223,22 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) k_
             const unsigned long long t = atomicAdd(&a.counters[kTileCounter], 1ull);
             sh.tile = t;
             if (t < ntiles) {
-                // Last range whose first tile is <= t.
+                // t is a visit position: the last visit entry starting at or
+                // before it names the range (entries of empty ranges share
+                // their successor's start, so the last one has tiles).
                 uint32_t lo = 0, hi = nranges;
                 while (hi - lo > 1) {
                     const uint32_t mid = (lo + hi) >> 1;
-                    if (a.ranges[mid].tile0 <= t)
+                    if (a.visit[mid].vstart <= t)
                         lo = mid;
                     else
                         hi = mid;
                 }
-                sh.range = lo;
-                const RangeDesc &d = a.ranges[lo];
-                const uint64_t k = t - d.tile0;
+                const uint32_t r = a.visit[lo].range;
+                sh.range = r;
+                const RangeDesc &d = a.ranges[r];
+                const uint64_t k = t - a.visit[lo].vstart;
+                sh.tile = d.tile0 + k;  // storage index of the tile
                 const uint32_t nw = (k + 1 == d.ntiles) ? d.last_words : pw;
                 const uint64_t tend = d.base + k * kValsPerWord * pw + kValsPerWord * nw;
                 // Primes p with p * p < tile end (Sec. 4: only primes up to

@@ -30,7 +30,7 @@ constexpr uint32_t kCompactThreads = 512;                   // one bitmap word p
 constexpr uint32_t kStagePerWave = 512;                     // compaction staging entries per wave
 constexpr uint32_t kFinalizeThreads = 1024;
 constexpr uint32_t kSegChunks = 4096;  // chunks per scan segment (4 per thread of 1024)
-constexpr uint32_t kBucketThreads = 256;    // primes per bucket work unit
+constexpr uint32_t kBucketThreads = 512;    // primes per bucket work unit
 constexpr uint32_t kBucketWindow = 2048;    // tiles per bucket work unit (LDS bins)
 constexpr uint32_t kBucketMinPrimes = 32768; // fewest large primes worth a bucket pass
 
@@ -74,6 +74,17 @@ struct JobHeader {
     uint64_t nseg;       // scan segments over all list ranges
 };
 
+// The order in which the sieve kernel's workgroups take tiles: ranges in
+// visit order, each contributing its tiles in storage order.  vstart is the
+// visit position of the range's first tile.  The host puts the ranges with
+// the most Table 1 starts per tile first, so the costliest tiles are not
+// left for the end of the job.
+struct VisitEntry {
+    uint64_t vstart;
+    uint32_t range;
+    uint32_t pad;
+};
+
 // Counters zeroed at the start of every job.
 enum Counter { kTileCounter = 0, kChunkCounter = 1, kErrorFlag = 2, kOverflowFlag = 3, kNumCounters = 4 };
 
@@ -93,6 +104,7 @@ struct PsGroup {
 struct SieveArgs {
     const JobHeader *job;
     const RangeDesc *ranges;
+    const VisitEntry *visit;      // nranges entries, in visit order
     unsigned long long *counters;
     unsigned long long *counts;   // per range
     const PrimeConst *prm;        // every resident prime >= 5, ascending
