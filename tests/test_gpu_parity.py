@@ -166,6 +166,36 @@ def test_list_batch_mixed_and_capacity(sv):
             assert np.array_equal(host[o:o + len(want[i])], want[i]), i
 
 
+def test_batch_visit_order_mixed(sv):
+    """Tiles are taken in a host-set visit order (most Table 1 starts per tile
+    first): empty ranges with large bounds sort first and share their
+    successor's visit position; costly single-tile ranges near 10^15 come
+    before long low ranges.  Results must not depend on that order."""
+    E = 10 ** 15
+    spec = [(E, E), (E + 7, E + 7), (5, 5), (E, E + 1), (E + 1, E + 60000),
+            (E + 3 * 10 ** 7, E + 3 * 10 ** 7 + 150000), (E // 4, E // 4 + 90000),
+            (10 ** 14 + 11, 10 ** 14 + 200011), (10 ** 9, 10 ** 9 + 5 * 10 ** 6),
+            (2, 4 * 10 ** 6 + 3), (10 ** 12, 10 ** 12 + 3 * 10 ** 6 + 1), (17, 18), (10 ** 11, 10 ** 11)]
+    random.Random(5).shuffle(spec)
+    lo = np.array([a for a, _ in spec], dtype=np.uint64)
+    hi = np.array([b for _, b in spec], dtype=np.uint64)
+    n = len(spec)
+    mode = (np.arange(n) % 2).astype(np.uint8)
+    sv.ensure_base_for(int(hi.max()))
+    want = [oracle.primes(int(a), int(b), elem_bytes=8, threads=4) for a, b in spec]
+    assert np.array_equal(sv.count_batch(lo, hi), np.array([len(w) for w in want], dtype=np.uint64))
+    cap = np.array([pkg.list_bound(int(a), int(b)) for a, b in spec], dtype=np.uint64)
+    off = np.concatenate([[0], np.cumsum(cap)[:-1]]).astype(np.uint64)
+    out = torch.zeros(int(cap.sum()) + 1, dtype=torch.int64, device="cuda")
+    counts, status = sv.list_batch(lo, hi, mode, out, off, cap, elem_bytes=8)
+    host = _u(out, 8)
+    for i in range(n):
+        assert int(counts[i]) == len(want[i]) and status[i] == 0, spec[i]
+        if mode[i]:
+            o = int(off[i])
+            assert np.array_equal(host[o:o + len(want[i])], want[i]), spec[i]
+
+
 def test_capacity_error_reports_count(sv):
     n_true = oracle.count(10 ** 6, 2 * 10 ** 6)
     out = torch.empty(10, dtype=torch.int64, device="cuda")
