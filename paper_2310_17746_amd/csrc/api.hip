@@ -27,7 +27,7 @@ hipError_t launch_zero(const JobHeader *job, unsigned long long *counters, unsig
                        uint32_t *bcount, hipStream_t s);
 hipError_t launch_bucket(const BucketArgs &a, int pass, uint32_t cus, hipStream_t s);
 hipError_t launch_bucket_scan(const BucketScanArgs &a, hipStream_t s);
-hipError_t launch_sieve(const SieveArgs &a, uint32_t nt, uint32_t grid, hipStream_t s);
+hipError_t launch_sieve(const SieveArgs &a, uint32_t nt, uint32_t grid, bool u24, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs &a, uint32_t grid, hipStream_t s);
 hipError_t launch_seg(const SegArgs &a, int pass, uint32_t grid, hipStream_t s);
 hipError_t launch_compact(const CompactArgs &a, uint32_t grid, hipStream_t s);
@@ -566,7 +566,7 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed)
     a.bcursor = c->d_bcursor.p;
     if (timed && (e = hipEventRecord(c->ev[0], s)) != hipSuccess)
         return e;
-    e = launch_sieve(a, c->prm.block_threads, (uint32_t)c->cus * c->prm.wg_per_cu, s);
+    e = launch_sieve(a, c->prm.block_threads, (uint32_t)c->cus * c->prm.wg_per_cu, c->sieve_u24 != 0, s);
     if (e != hipSuccess)
         return e;
     if (timed && (e = hipEventRecord(c->ev[1], s)) != hipSuccess)
@@ -699,6 +699,17 @@ int run_job_once(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *h
     if (e != hipSuccess)
         return hip_status(e);
     const bool buckets = pl.nunits != 0;
+    {
+        // 24-bit start arithmetic when every range's primes are below 2^24 - 8
+        uint64_t top = 0;
+        for (uint64_t i = 0; i < n; ++i)
+            top = std::max(top, pl.ranges[i].hi);
+        const uint32_t u24 = (top < 2 || isqrt_host(top - 1) < (1u << 24) - 8) ? 1u : 0u;
+        if (u24 != c->sieve_u24) {
+            c->sieve_u24 = u24;
+            c->gen++;
+        }
+    }
     if (buckets) {
         // LDS bins for the largest window of the job, in power-of-two steps
         // so that captured graphs (which hold the size) are seldom re-made

@@ -197,7 +197,9 @@ struct TileShared {
 
 // Three 512-thread workgroups per CU (24 waves, 6 per SIMD) need at most 80
 // VGPRs; the attribute holds the compiler to that.
-template <int NT>
+// U24: every active prime of the job is below 2^24 - 8, so the Table 1
+// starts and the per-item products use the full-rate 24-bit multiplier.
+template <int NT, bool U24>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) k_sieve(SieveArgs a)
 {
     extern __shared__ uint32_t lds[];
@@ -340,9 +342,16 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) k_
                 if (pc.p > sqe)
                     continue;  // P * P >= tile end: nothing to mark
                 uint32_t id1, id5;
-                tile_start(pc, sqb, Bm1, B32, narrow, id1, id5);
-                const uint32_t step = g * pc.p;
-                const uint32_t off = j * pc.p;
+                uint32_t step, off;
+                if (U24) {
+                    tile_start_u24(pc, sqb, Bm1, B32, narrow, id1, id5);
+                    step = __umul24(g, pc.p & 0xFFFFFFu);  // g, j < 2^16
+                    off = __umul24(j, pc.p & 0xFFFFFFu);
+                } else {
+                    tile_start(pc, sqb, Bm1, B32, narrow, id1, id5);
+                    step = g * pc.p;
+                    off = j * pc.p;
+                }
                 if (v < n_dense) {
                     // g is a multiple of 32: fixed-mask marking
                     mark_plane_fixed(id1 + off, step, nbits);
@@ -997,14 +1006,15 @@ __global__ void k_zero(const JobHeader *job, unsigned long long *counters, unsig
 hipError_t set_sieve_lds_limit(uint32_t segment_bytes)
 {
     const int bytes = (int)(segment_bytes + sizeof(TileShared));
-    hipError_t e;
-    e = hipFuncSetAttribute((const void *)k_sieve<256>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess)
-        return e;
-    e = hipFuncSetAttribute((const void *)k_sieve<512>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess)
-        return e;
-    return hipFuncSetAttribute((const void *)k_sieve<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    const void *fns[] = {(const void *)k_sieve<256, false>, (const void *)k_sieve<512, false>,
+                         (const void *)k_sieve<1024, false>, (const void *)k_sieve<256, true>,
+                         (const void *)k_sieve<512, true>, (const void *)k_sieve<1024, true>};
+    for (const void *f : fns) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_zero(const JobHeader *job, unsigned long long *counters, unsigned long long *counts,
@@ -1063,23 +1073,35 @@ hipError_t launch_bucket_scan(const BucketScanArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_sieve(const SieveArgs &a, uint32_t nt, uint32_t grid, hipStream_t s)
+namespace {
+
+template <bool U24>
+hipError_t launch_sieve_t(const SieveArgs &a, uint32_t nt, uint32_t grid, size_t lds, hipStream_t s)
 {
-    const size_t lds = (size_t)a.pw * 8 + sizeof(TileShared);  // planes, then bookkeeping
     switch (nt) {
     case 256:
-        hipLaunchKernelGGL(k_sieve<256>, dim3(grid), dim3(256), lds, s, a);
+        hipLaunchKernelGGL((k_sieve<256, U24>), dim3(grid), dim3(256), lds, s, a);
         break;
     case 512:
-        hipLaunchKernelGGL(k_sieve<512>, dim3(grid), dim3(512), lds, s, a);
+        hipLaunchKernelGGL((k_sieve<512, U24>), dim3(grid), dim3(512), lds, s, a);
         break;
     case 1024:
-        hipLaunchKernelGGL(k_sieve<1024>, dim3(grid), dim3(1024), lds, s, a);
+        hipLaunchKernelGGL((k_sieve<1024, U24>), dim3(grid), dim3(1024), lds, s, a);
         break;
     default:
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+}  // namespace
+
+// u24: the caller guarantees that every prime a tile of the job uses is
+// below 2^24 - 8 (isqrt(hi - 1) below that for every range).
+hipError_t launch_sieve(const SieveArgs &a, uint32_t nt, uint32_t grid, bool u24, hipStream_t s)
+{
+    const size_t lds = (size_t)a.pw * 8 + sizeof(TileShared);  // planes, then bookkeeping
+    return u24 ? launch_sieve_t<true>(a, nt, grid, lds, s) : launch_sieve_t<false>(a, nt, grid, lds, s);
 }
 
 hipError_t launch_finalize(const FinalizeArgs &a, uint32_t grid, hipStream_t s)

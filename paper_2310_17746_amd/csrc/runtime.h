@@ -75,6 +75,7 @@ struct sieve_ctx {
     uint64_t bucket_fallbacks = 0;   // jobs re-run with the exact bucket layout
     uint64_t bucket_budget = 0;      // bucket entries one job may hold (larger jobs run in pieces)
     uint32_t bucket_win = 0;         // per-tile LDS bins of the bucket kernels (kernel argument)
+    uint32_t sieve_u24 = 0;          // the job's primes are below 2^24 - 8: 24-bit start arithmetic
 
     // Presieve tables.
     sieve::rt::DevBuf<uint2> d_pstab;

@@ -181,4 +181,40 @@ __device__ inline void tile_start(const PrimeConst &pc, uint32_t sqb, uint64_t B
     table1_ids(dp, R, p5, id1, id5);
 }
 
+// tile_start for tiles whose active primes are all below 2^24 - 8 (so R,
+// dp, i0 and the per-prime products fit 24 bits).  The same arithmetic with
+// every product formed by the full-rate 24-bit multiplier: i0 = dp div 6 as
+// (dp * ceil(2^26 / 6)) >> 26, exact for dp < 2^25, and k R with R < 2^22.
+// The remainder keeps the 64-bit reciprocal.
+__device__ inline void tile_start_u24(const PrimeConst &pc, uint32_t sqb, uint64_t Bm1, uint32_t B32, bool narrow,
+                                      uint32_t &id1, uint32_t &id5)
+{
+    const uint32_t P = pc.p & 0xFFFFFFu;
+    const uint32_t R = pc.r & 0xFFFFFFu;
+    const bool p5 = (pc.m_hi & kP5Flag) != 0;
+    uint32_t dp;
+    if (P > sqb) {
+        dp = __umul24(P, P) - B32 + (p5 ? 1u : 5u);
+    } else {
+        const uint32_t rem = narrow ? mod_narrow((uint32_t)Bm1, (uint32_t)(Bm1 >> 32), pc.p, pc.m_lo,
+                                                 pc.m_hi & ~kP5Flag)
+                                    : mod_invariant(Bm1, pc.p, prime_recip(pc), false);
+        dp = P + (p5 ? 0u : 4u) - rem;
+    }
+    dp &= 0xFFFFFFu;  // below 2^24 by the bound on P
+    constexpr uint32_t kM6 = 11184811u;  // ceil(2^26 / 6)
+    const uint32_t i0 = (uint32_t)(((uint64_t)dp * kM6) >> 26);  // 24 x 24-bit product
+    // 6 i0 on the 24-bit multiplier (written out: the compiler would fold
+    // dp - 6 i0 into a 32-bit multiply by -6)
+    uint32_t i6;
+    asm("v_mul_u32_u24 %0, %1, 6" : "=v"(i6) : "v"(i0));
+    const uint32_t q = dp - i6;
+    const uint64_t t1 = p5 ? kTable1_id1_p5 : kTable1_id1_p1;
+    const uint64_t t5 = p5 ? kTable1_id5_p5 : kTable1_id5_p1;
+    const uint32_t e1 = (uint32_t)(t1 >> (8u * q));
+    const uint32_t e5 = (uint32_t)(t5 >> (8u * q));
+    id1 = i0 + __umul24(e1 & 7u, R) + ((e1 >> 3) & 7u) - 1u;
+    id5 = i0 + __umul24(e5 & 7u, R) + ((e5 >> 3) & 7u) - 1u;
+}
+
 }  // namespace sieve
