@@ -894,13 +894,20 @@ __device__ __forceinline__ void lds_barrier()
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// Hand-off of LDS data between lanes of one wavefront: its LDS operations
+// complete, and the compiler moves no memory access across it.
+__device__ __forceinline__ void wave_lds_fence()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kCompactThreads) k_compact(CompactArgs a)
 {
     constexpr uint32_t kW = kCompactThreads / kWave;
-    constexpr uint32_t kU = 4;  // contiguous chunks per workgroup iteration
-    __shared__ T s_stage[kW][kStagePerWave];
-    __shared__ uint32_t s_wt[kW];
+    constexpr uint32_t kU = 2;  // contiguous chunks per workgroup iteration
+    __shared__ T s_stage[kW][kStagePerWave];  // one staging window per wavefront
+    __shared__ uint32_t s_wt[2][kW];              // per-wave totals, alternating per chunk
     __shared__ unsigned long long s_meta[2][kU];  // output offset, value base
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1);
@@ -920,7 +927,13 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(CompactArgs a)
 
     // Each iteration takes kU contiguous chunks.  Their loads are issued
     // together at the top; the stores of all kU chunks stay in flight until
-    // the next iteration's loads are waited for.
+    // the next iteration's loads are waited for.  Per chunk, the only
+    // workgroup barrier is the exchange of the per-wave totals; staging and
+    // storing touch only the wave's own window.  The totals alternate between
+    // two buffers per processed chunk: a wave writes a buffer again only after
+    // the barrier of the chunk in between, which every wave reaches after it
+    // has read that buffer.
+    uint32_t par = 0;
     for (uint64_t c0 = (uint64_t)blockIdx.x * kU; c0 < nchunks; c0 += (uint64_t)gridDim.x * kU) {
         uint64_t mu[kU];
 #pragma unroll
@@ -947,20 +960,20 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(CompactArgs a)
             const uint64_t m = mu[u];
             const uint32_t cnt = __popcll(m);
             const uint32_t incl = wave_incl_scan(cnt, lane);
+            uint32_t *const wt = s_wt[par];
+            par ^= 1u;
             if (lane == kWave - 1)
-                s_wt[wave] = incl;
+                wt[wave] = incl;
             lds_barrier();
-            uint32_t woff = 0, wmax = 0;
-            for (uint32_t q = 0; q < kW; ++q) {
-                woff += q < wave ? s_wt[q] : 0u;
-                wmax = s_wt[q] > wmax ? s_wt[q] : wmax;
-            }
-            const uint32_t wtot = s_wt[wave];
+            uint32_t woff = 0;
+            for (uint32_t q = 0; q < kW; ++q)
+                woff += q < wave ? wt[q] : 0u;
+            const uint32_t wtot = wt[wave];
             const uint64_t obase = coff + woff;
             const uint64_t vb = s_meta[1][u] + kValsPerWord * tid;
             const uint32_t excl = incl - cnt;
-            // Passes over rank windows of kStagePerWave, uniform across the block.
-            for (uint32_t pass = 0; pass < wmax; pass += kStagePerWave) {
+            // Passes over rank windows of kStagePerWave, uniform across the wavefront.
+            for (uint32_t pass = 0; pass < wtot; pass += kStagePerWave) {
                 if (excl < pass + kStagePerWave && excl + cnt > pass) {
                     uint64_t mm = m;
                     uint32_t pos = excl;
@@ -972,15 +985,12 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(CompactArgs a)
                         ++pos;
                     }
                 }
-                lds_barrier();
-                if (wtot > pass) {
-                    const uint32_t n_in = (wtot - pass) < kStagePerWave ? (wtot - pass) : kStagePerWave;
-                    for (uint32_t e = lane; e < n_in; e += kWave)
-                        out[obase + pass + e] = s_stage[wave][e];
-                }
-                lds_barrier();
+                wave_lds_fence();  // the window is written before any lane reads it
+                const uint32_t n_in = (wtot - pass) < kStagePerWave ? (wtot - pass) : kStagePerWave;
+                for (uint32_t e = lane; e < n_in; e += kWave)
+                    out[obase + pass + e] = s_stage[wave][e];
+                wave_lds_fence();  // and read before the next pass rewrites it
             }
-            lds_barrier();  // every wave has read s_wt before the next chunk rewrites it
         }
         lds_barrier();  // s_meta is rewritten by the next iteration
     }
