@@ -238,6 +238,8 @@ def test_error_paths(sv):
     dict(dense_hits=pkg.DENSE_NEVER),                           # no fixed-mask marking
     dict(dense_hits=40, split_hits=8, segment_bytes=8192),      # fixed-mask marking for most primes
     dict(dense_hits=2000, cofactor_skip=pkg.SKIP_ALL),          # fixed-mask beside the skip path
+    dict(split_hits=8),                                         # dense lane counts up to 384
+    dict(segment_bytes=159744, split_hits=8),                   # dense lane counts up to 1184
 ])
 def test_parameter_grid_parity(params):
     with pkg.Sieve(0, params) as s:
