@@ -24,7 +24,7 @@
 namespace sieve {
 hipError_t set_sieve_lds_limit(uint32_t bytes);
 hipError_t launch_zero(const JobHeader *job, unsigned long long *counters, unsigned long long *counts,
-                       uint32_t *bcount, hipStream_t s);
+                       uint32_t *bcount, uint32_t *gbm, uint32_t *garrive, hipStream_t s);
 hipError_t launch_bucket(const BucketArgs &a, int pass, uint32_t cus, hipStream_t s);
 hipError_t launch_bucket_scan(const BucketScanArgs &a, hipStream_t s);
 hipError_t launch_sieve(const SieveArgs &a, uint32_t nt, uint32_t grid, bool u24, hipStream_t s);
@@ -291,6 +291,7 @@ struct Plan {
     uint64_t ntiles = 0, nchunks = 0, nunits = 0, nseg = 0;
     uint64_t best = 0;  // bucket entries of the estimated layout
     uint32_t bwin = 0;  // most tiles in one bucket window
+    uint64_t nvisit = 0, gtiles = 0;  // sieve work units; tiles of split ranges
 };
 
 int make_plan(const sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, const uint8_t *mode,
@@ -347,6 +348,7 @@ int make_plan(const sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t
             d.bbase = pl.best;
             pl.best += (uint64_t)d.bcap * nt;
         }
+        d.nparts = 1;  // split tiles are chosen below, once the job's size is known
         d.mode = lst ? 1u : 0u;
         if (lst) {
             d.out_off = off ? off[i] : 0;
@@ -367,6 +369,29 @@ int make_plan(const sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t
             return SIEVE_E_INVAL;
         d.seg0 = (uint32_t)pl.nseg;
         pl.nseg += d.nseg;
+    }
+    // Split tiles.  A tile's own loop starts min(nact, kbig) primes; one whose
+    // loop is far longer than a resident workgroup's share of the whole job
+    // would finish last, so its primes beyond the split items go to parts of
+    // C = max(kPartPrimes, share) primes, each on its own workgroup (part 0
+    // also takes the items); their marks meet in a global copy of the planes.
+    double starts = 0;
+    for (uint64_t i = 0; i < n; ++i)
+        starts += (double)pl.ranges[i].ntiles * std::min(pl.ranges[i].nact, pl.ranges[i].kbig);
+    const double share = starts / ((double)c->cus * c->prm.wg_per_cu);
+    const uint32_t C = (uint32_t)std::min(std::max((double)kPartPrimes, share), 2.0e9);
+    for (uint64_t i = 0; i < n; ++i) {
+        RangeDesc &d = pl.ranges[i];
+        const uint32_t n_loop = std::min(d.nact, d.kbig);
+        if (d.ntiles && n_loop > c->k_split && (uint64_t)(n_loop - c->k_split) > 2ull * C) {
+            if (pl.gtiles + d.ntiles > 0xFFFFFFFFull)
+                return SIEVE_E_INVAL;
+            d.nparts = (uint32_t)(((uint64_t)n_loop - c->k_split + C - 1) / C);
+            d.part_primes = C;
+            d.gtile0 = (uint32_t)pl.gtiles;
+            pl.gtiles += d.ntiles;
+        }
+        pl.nvisit += (uint64_t)d.ntiles * d.nparts;
     }
     return SIEVE_OK;
 }
@@ -395,7 +420,7 @@ uint64_t grow(uint64_t cur, uint64_t need, uint64_t floor_)
 
 // Makes the scratch hold a job of the given size.  Capacities only grow; any
 // reallocation bumps c->gen so that captured graphs are re-made.
-int ensure_capacity(sieve_ctx *c, uint64_t nranges, uint64_t nchunks, uint64_t ntiles)
+int ensure_capacity(sieve_ctx *c, uint64_t nranges, uint64_t nchunks, uint64_t ntiles, uint64_t gtiles)
 {
     bool changed = false;
     if (nranges > c->cap_ranges || !c->d_blob.p) {
@@ -449,6 +474,15 @@ int ensure_capacity(sieve_ctx *c, uint64_t nranges, uint64_t nchunks, uint64_t n
         c->d_boff.release();
         if (!c->d_bcount.reserve(c->cap_tiles) || !c->d_bcursor.reserve(c->cap_tiles) ||
             !c->d_boff.reserve(c->cap_tiles + 1))
+            return SIEVE_E_NOMEM;
+        changed = true;
+    }
+    if (gtiles > c->cap_gtiles || !c->d_garrive.p) {
+        c->cap_gtiles = grow(c->cap_gtiles, gtiles, 16);
+        c->d_gbm.release();
+        c->d_garrive.release();
+        if (!c->d_gbm.reserve(c->cap_gtiles * 2 * (c->prm.segment_bytes / 8)) ||
+            !c->d_garrive.reserve(c->cap_gtiles))
             return SIEVE_E_NOMEM;
         changed = true;
     }
@@ -510,7 +544,8 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed)
             return e;
         // per-tile counts (exact layout) or cursors (estimated layout) start at 0
         uint32_t *bzero = phase == kPhaseDirect ? c->d_bcursor.p : c->d_bcount.p;
-        if ((e = launch_zero(job, c->d_counters.p, c->d_counts.p, bzero, s)) != hipSuccess)
+        if ((e = launch_zero(job, c->d_counters.p, c->d_counts.p, bzero, c->d_gbm.p, c->d_garrive.p, s)) !=
+            hipSuccess)
             return e;
     }
     if (phase == kPhaseBucketCount) {
@@ -538,6 +573,8 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed)
     a.job = job;
     a.ranges = ranges;
     a.visit = (const VisitEntry *)(c->d_blob.p + L.visit);
+    a.gbm = c->d_gbm.p;
+    a.garrive = c->d_garrive.p;
     a.counters = c->d_counters.p;
     a.counts = c->d_counts.p;
     a.prm = c->d_prm.p;
@@ -656,7 +693,7 @@ int run_job_once(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *h
     const uint64_t nlist = pl.nlist;
     if (nlist && !out)
         return SIEVE_E_INVAL;
-    st = ensure_capacity(c, n, pl.nchunks, pl.ntiles);
+    st = ensure_capacity(c, n, pl.nchunks, pl.ntiles, pl.gtiles);
     if (st != SIEVE_OK)
         return st;
     hipStream_t s = stream ? stream : c->stream;
@@ -667,6 +704,9 @@ int run_job_once(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *h
     h->nchunks = pl.nchunks;
     h->nunits = pl.nunits;
     h->nseg = pl.nseg;
+    h->nvisit = pl.nvisit;
+    h->gtiles = pl.gtiles;
+    h->gwords = pl.gtiles * 2 * (c->prm.segment_bytes / 8);
     h->bmode = 1;
     h->nranges = (uint32_t)n;
     h->nlist = (uint32_t)nlist;
@@ -674,21 +714,24 @@ int run_job_once(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *h
     h->elem_bytes = elem_bytes;
     if (n) {
         memcpy(c->h_blob + L.ranges, pl.ranges.data(), n * sizeof(RangeDesc));
-        // Visit order: most Table 1 starts per tile first (kbig is the
-        // number of primes a tile of the range starts in the tile), ties in
-        // storage order.
+        // Visit order: most Table 1 starts per work unit first (a tile of
+        // an unsplit range starts min(nact, kbig) primes, a part of a split
+        // tile about part_primes), ties in storage order.
         std::vector<uint32_t> ord(n);
-        for (uint64_t i = 0; i < n; ++i)
+        std::vector<uint32_t> key(n);
+        for (uint64_t i = 0; i < n; ++i) {
             ord[i] = (uint32_t)i;
-        std::stable_sort(ord.begin(), ord.end(),
-                         [&](uint32_t x, uint32_t y) { return pl.ranges[x].kbig > pl.ranges[y].kbig; });
+            const RangeDesc &d = pl.ranges[i];
+            key[i] = d.nparts > 1 ? d.part_primes : std::min(d.nact, d.kbig);
+        }
+        std::stable_sort(ord.begin(), ord.end(), [&](uint32_t x, uint32_t y) { return key[x] > key[y]; });
         VisitEntry *v = (VisitEntry *)(c->h_blob + L.visit);
         uint64_t pos = 0;
         for (uint64_t j = 0; j < n; ++j) {
             v[j].vstart = pos;
             v[j].range = ord[j];
             v[j].pad = 0;
-            pos += pl.ranges[ord[j]].ntiles;
+            pos += (uint64_t)pl.ranges[ord[j]].ntiles * pl.ranges[ord[j]].nparts;
         }
     }
     hipError_t e = hipMemcpyAsync(c->d_blob.p, c->h_blob, L.ranges + n * sizeof(RangeDesc),
@@ -1116,7 +1159,7 @@ int sieve_create(sieve_ctx **out, int device, const sieve_params *p)
     if (st == SIEVE_OK)
         st = install_primes(c, 0);
     if (st == SIEVE_OK)
-        st = ensure_capacity(c, 1, 1, 1);
+        st = ensure_capacity(c, 1, 1, 1, 1);
     if (st != SIEVE_OK) {
         destroy_ctx(c);
         return st;

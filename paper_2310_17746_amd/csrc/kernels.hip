@@ -1,7 +1,8 @@
 // Device kernels of the segmented wheel sieve (gfx950, wave64).
 //
-// k_zero       clears the job's counters, counts and bucket cursors (a kernel,
-//              so that the whole job can be captured in a graph).
+// k_zero       clears the job's counters, counts, bucket cursors and the
+//              split tiles' global planes (a kernel, so that the whole job
+//              can be captured in a graph).
 // k_bucket     bucket sieve for the large primes of multi-tile ranges: walks
 //              each prime's hits tile by tile and bins them per tile (count,
 //              scan and fill passes for the exact layout; one fill pass into
@@ -10,7 +11,8 @@
 //              LDS: presieve init, Table 1 starts + marking of the remaining
 //              base primes, the tile's bucket entries, edge masks, then either
 //              a popcount into the range's count or a value-ordered bitmap +
-//              per-chunk counts.
+//              per-chunk counts.  A split tile's parts run on several
+//              workgroups and meet in a global copy of the planes.
 // k_seg_sum    per scan segment (4096 chunks of a list range): chunk-count sum.
 // k_finalize   per range: adds 2 and 3 when in range, scans the segment sums
 //              of list ranges into segment output bases, sets count and status.
@@ -193,6 +195,8 @@ struct TileShared {
     uint32_t psoff[kMaxGroups];
     uint32_t red[1024 / 64];
     uint32_t chunk[64];
+    uint32_t part;  // split tiles: this workgroup's part
+    uint32_t last;  // split tiles: this workgroup finished the tile's last part
 };
 
 // Three 512-thread workgroups per CU (24 waves, 6 per SIMD) need at most 80
@@ -212,6 +216,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) k_
     const uint32_t base5 = 4 * pw;  // LDS byte address of A_five
     TileShared &sh = *reinterpret_cast<TileShared *>(lds + 2 * pw);
     const uint64_t ntiles = a.job->ntiles;
+    const uint64_t nvisit = a.job->nvisit;
     const uint32_t nranges = a.job->nranges;
     if ((uint32_t)(size_t)(__attribute__((address_space(3))) void *)lds != 0) {
         // Marks assume the planes at LDS address 0; report and do nothing.
@@ -223,8 +228,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) k_
     for (;;) {
         if (tid == 0) {
             const unsigned long long t = atomicAdd(&a.counters[kTileCounter], 1ull);
-            sh.tile = t;
-            if (t < ntiles) {
+            sh.tile = ntiles;  // none left
+            if (t < nvisit) {
                 // t is a visit position: the last visit entry starting at or
                 // before it names the range (entries of empty ranges share
                 // their successor's start, so the last one has tiles).
@@ -239,7 +244,10 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) k_
                 const uint32_t r = a.visit[lo].range;
                 sh.range = r;
                 const RangeDesc &d = a.ranges[r];
-                const uint64_t k = t - a.visit[lo].vstart;
+                // unit u of the range: tile u / nparts, part u mod nparts
+                const uint64_t u = t - a.visit[lo].vstart;
+                const uint64_t k = d.nparts > 1 ? u / d.nparts : u;
+                sh.part = (uint32_t)(u - k * d.nparts);
                 sh.tile = d.tile0 + k;  // storage index of the tile
                 const uint32_t nw = (k + 1 == d.ntiles) ? d.last_words : pw;
                 const uint64_t tend = d.base + k * kValsPerWord * pw + kValsPerWord * nw;
@@ -273,118 +281,195 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) k_
         const uint64_t tend = B + kValsPerWord * nwords;
         const uint32_t nbits = nwords * 32;
 
-        // ---- presieve init: OR of the repeating composite patterns -------
-        if (tid < kMaxGroups)
-            sh.psoff[tid] = (uint32_t)((B / 6) % a.groups[tid].period);
-        __syncthreads();
-        {
-            // Every group is always applied; a disabled group has an all-zero
-            // table, so the loop has no data-dependent branches.
-            uint32_t o[kMaxGroups];
-#pragma unroll
-            for (int g = 0; g < kMaxGroups; ++g)
-                o[g] = (sh.psoff[g] + 32u * tid) % a.groups[g].period;
-            for (uint32_t w = tid; w < nwords; w += NT) {
-                uint2 x[kMaxGroups], y[kMaxGroups];
-#pragma unroll
-                for (int g = 0; g < kMaxGroups; ++g) {
-                    const uint2 *tb = a.ps_tab + a.groups[g].offset + (o[g] >> 5);
-                    x[g] = tb[0];
-                    y[g] = tb[1];
+        const uint32_t part = sh.part;
+        const bool split = d.nparts > 1;
+        if (part == 0) {
+            // ---- presieve init: OR of the repeating composite patterns -------
+            if (tid < kMaxGroups)
+                sh.psoff[tid] = (uint32_t)((B / 6) % a.groups[tid].period);
+            __syncthreads();
+            {
+                // Every group is always applied; a disabled group has an all-zero
+                // table, so the loop has no data-dependent branches.
+                uint32_t o[kMaxGroups];
+    #pragma unroll
+                for (int g = 0; g < kMaxGroups; ++g)
+                    o[g] = (sh.psoff[g] + 32u * tid) % a.groups[g].period;
+                for (uint32_t w = tid; w < nwords; w += NT) {
+                    uint2 x[kMaxGroups], y[kMaxGroups];
+    #pragma unroll
+                    for (int g = 0; g < kMaxGroups; ++g) {
+                        const uint2 *tb = a.ps_tab + a.groups[g].offset + (o[g] >> 5);
+                        x[g] = tb[0];
+                        y[g] = tb[1];
+                    }
+                    uint2 c = make_uint2(0, 0);
+    #pragma unroll
+                    for (int g = 0; g < kMaxGroups; ++g) {
+                        const uint32_t sft = o[g] & 31;
+                        c.x |= __builtin_amdgcn_alignbit(y[g].x, x[g].x, sft);
+                        c.y |= __builtin_amdgcn_alignbit(y[g].y, x[g].y, sft);
+                        o[g] += a.groups[g].step;
+                        o[g] = o[g] >= a.groups[g].period ? o[g] - a.groups[g].period : o[g];
+                    }
+                    pl1[w] = c.x;
+                    pl5[w] = c.y;
                 }
-                uint2 c = make_uint2(0, 0);
-#pragma unroll
-                for (int g = 0; g < kMaxGroups; ++g) {
-                    const uint32_t sft = o[g] & 31;
-                    c.x |= __builtin_amdgcn_alignbit(y[g].x, x[g].x, sft);
-                    c.y |= __builtin_amdgcn_alignbit(y[g].y, x[g].y, sft);
-                    o[g] += a.groups[g].step;
-                    o[g] = o[g] >= a.groups[g].period ? o[g] - a.groups[g].period : o[g];
-                }
-                pl1[w] = c.x;
-                pl5[w] = c.y;
             }
-        }
-        __syncthreads();
+            __syncthreads();
 
-        // ---- marking: Table 1 starts, stride P in each plane -------------
-        {
-            // Primes from d.kbig on come from this tile's bucket instead.
+            // ---- marking: Table 1 starts, stride P in each plane -------------
+            {
+                // Primes from d.kbig on come from this tile's bucket instead.
+                const uint32_t n_act = sh.nact < d.kbig ? sh.nact : d.kbig;
+                const uint32_t ks = n_act < a.k_split ? n_act : a.k_split;
+                const uint32_t n_items = ks > a.first_mark ? a.item_prefix[ks - a.first_mark] : 0;
+                const uint32_t kd = n_act < a.k_dense ? n_act : a.k_dense;
+                const uint32_t n_dense = kd > a.first_mark ? a.item_prefix[kd - a.first_mark] : 0;
+                uint32_t n_rest = n_act > a.k_split ? n_act - a.k_split : 0;
+                if (split && n_rest > d.part_primes)
+                    n_rest = d.part_primes;  // part 0 of a split tile: its share of the rest
+                const uint32_t n_work = n_items + n_rest;
+                // Every active prime is below 2^31 when the tile ends below 2^62.
+                const bool narrow = tend <= (1ull << 62);
+                const uint32_t b5 = (uint32_t)(B % 5);
+                const uint32_t sqb = sh.sqb, sqe = sh.sqe;
+                const uint64_t Bm1 = B - 1;
+                const uint32_t B32 = (uint32_t)B;
+                // Plane A_five is addressed as bits [32 pw, 32 pw + nbits) of one
+                // array that starts with A_one, so a mark needs no base add.
+                const uint32_t off5 = 32u * pw;
+                for (uint32_t v = tid; v < n_work; v += NT) {
+                    uint32_t kp, j, g;
+                    if (v < n_items) {
+                        const uint2 it = a.items[v];
+                        kp = it.x;
+                        j = it.y >> 16;
+                        g = it.y & 0xFFFFu;
+                    } else {
+                        kp = a.k_split + (v - n_items);
+                        j = 0;
+                        g = 1;
+                    }
+                    const PrimeConst pc = a.prm[kp];
+                    if (pc.p > sqe)
+                        continue;  // P * P >= tile end: nothing to mark
+                    uint32_t id1, id5;
+                    uint32_t step, off;
+                    if (U24) {
+                        tile_start_u24(pc, sqb, Bm1, B32, narrow, id1, id5);
+                        step = __umul24(g, pc.p & 0xFFFFFFu);  // g, j < 2^16
+                        off = __umul24(j, pc.p & 0xFFFFFFu);
+                    } else {
+                        tile_start(pc, sqb, Bm1, B32, narrow, id1, id5);
+                        step = g * pc.p;
+                        off = j * pc.p;
+                    }
+                    if (v < n_dense) {
+                        // g is a multiple of 32: fixed-mask marking
+                        mark_plane_fixed(id1 + off, step, nbits);
+                        mark_plane_fixed(id5 + off + off5, step, nbits + off5);
+                    } else if (a.skip5 == 1 || (a.skip5 == 2 && v < n_items)) {
+                        // hit n of this lane has cofactor m0 + 6(j + n g) = c + n g (mod 5);
+                        // it is a multiple of 5 when n = -c / g (mod 5)
+                        const uint32_t inv5 = pc.r >> 29;
+                        const uint32_t ginv = inv_mod5(g);
+                        const uint32_t c1 = (cofactor_mod5(b5, id1, 1, inv5) + j) % 5u;
+                        const uint32_t c5 = (cofactor_mod5(b5, id5, 0, inv5) + j) % 5u;
+                        mark_plane_skip5(0, id1 + off, step, nbits, ((5u - c1) * ginv) % 5u);
+                        mark_plane_skip5(0, id5 + off + off5, step, nbits + off5, ((5u - c5) * ginv) % 5u);
+                    } else {
+                        mark_plane(0, id1 + off, step, nbits);
+                        mark_plane(0, id5 + off + off5, step, nbits + off5);
+                    }
+                }
+                // Bucket entries of this tile: one mark each.
+                if (d.kbig < d.nact) {
+                    const bool est = a.job->bmode == 1;
+                    const uint64_t e0 = est ? d.bbase + k * d.bcap : a.boff[t];
+                    uint64_t ne = est ? a.bcursor[t] : a.bcount[t];
+                    if (est && ne > d.bcap)
+                        ne = d.bcap;  // overflowed slice: the job is run again exactly
+                    for (uint64_t e = tid; e < ne; e += NT) {
+                        const uint32_t v = a.bdata[e0 + e];
+                        const uint32_t bit = v & 0x7FFFFFFFu;
+                        lds_or(((bit >> 3) & ~3u) + ((v >> 31) ? base5 : 0u), 1u << (bit & 31));
+                    }
+                }
+            }
+            __syncthreads();
+
+        } else {
+            // ---- a later part of a split tile: primes k_split + [part C,
+            // (part + 1) C) with C = d.part_primes, marked straight into the
+            // tile's global planes (they are large: few hits each)
             const uint32_t n_act = sh.nact < d.kbig ? sh.nact : d.kbig;
-            const uint32_t ks = n_act < a.k_split ? n_act : a.k_split;
-            const uint32_t n_items = ks > a.first_mark ? a.item_prefix[ks - a.first_mark] : 0;
-            const uint32_t kd = n_act < a.k_dense ? n_act : a.k_dense;
-            const uint32_t n_dense = kd > a.first_mark ? a.item_prefix[kd - a.first_mark] : 0;
             const uint32_t n_rest = n_act > a.k_split ? n_act - a.k_split : 0;
-            const uint32_t n_work = n_items + n_rest;
-            // Every active prime is below 2^31 when the tile ends below 2^62.
+            const uint32_t C = d.part_primes;
+            const uint32_t r0 = part * C;
+            const uint32_t r1 = n_rest < r0 + C ? n_rest : r0 + C;
             const bool narrow = tend <= (1ull << 62);
-            const uint32_t b5 = (uint32_t)(B % 5);
             const uint32_t sqb = sh.sqb, sqe = sh.sqe;
             const uint64_t Bm1 = B - 1;
             const uint32_t B32 = (uint32_t)B;
-            // Plane A_five is addressed as bits [32 pw, 32 pw + nbits) of one
-            // array that starts with A_one, so a mark needs no base add.
-            const uint32_t off5 = 32u * pw;
-            for (uint32_t v = tid; v < n_work; v += NT) {
-                uint32_t kp, j, g;
-                if (v < n_items) {
-                    const uint2 it = a.items[v];
-                    kp = it.x;
-                    j = it.y >> 16;
-                    g = it.y & 0xFFFFu;
-                } else {
-                    kp = a.k_split + (v - n_items);
-                    j = 0;
-                    g = 1;
-                }
-                const PrimeConst pc = a.prm[kp];
-                if (pc.p > sqe)
-                    continue;  // P * P >= tile end: nothing to mark
-                uint32_t id1, id5;
-                uint32_t step, off;
-                if (U24) {
-                    tile_start_u24(pc, sqb, Bm1, B32, narrow, id1, id5);
-                    step = __umul24(g, pc.p & 0xFFFFFFu);  // g, j < 2^16
-                    off = __umul24(j, pc.p & 0xFFFFFFu);
-                } else {
-                    tile_start(pc, sqb, Bm1, B32, narrow, id1, id5);
-                    step = g * pc.p;
-                    off = j * pc.p;
-                }
-                if (v < n_dense) {
-                    // g is a multiple of 32: fixed-mask marking
-                    mark_plane_fixed(id1 + off, step, nbits);
-                    mark_plane_fixed(id5 + off + off5, step, nbits + off5);
-                } else if (a.skip5 == 1 || (a.skip5 == 2 && v < n_items)) {
-                    // hit n of this lane has cofactor m0 + 6(j + n g) = c + n g (mod 5);
-                    // it is a multiple of 5 when n = -c / g (mod 5)
-                    const uint32_t inv5 = pc.r >> 29;
-                    const uint32_t ginv = inv_mod5(g);
-                    const uint32_t c1 = (cofactor_mod5(b5, id1, 1, inv5) + j) % 5u;
-                    const uint32_t c5 = (cofactor_mod5(b5, id5, 0, inv5) + j) % 5u;
-                    mark_plane_skip5(0, id1 + off, step, nbits, ((5u - c1) * ginv) % 5u);
-                    mark_plane_skip5(0, id5 + off + off5, step, nbits + off5, ((5u - c5) * ginv) % 5u);
-                } else {
-                    mark_plane(0, id1 + off, step, nbits);
-                    mark_plane(0, id5 + off + off5, step, nbits + off5);
-                }
-            }
-            // Bucket entries of this tile: one mark each.
-            if (d.kbig < d.nact) {
-                const bool est = a.job->bmode == 1;
-                const uint64_t e0 = est ? d.bbase + k * d.bcap : a.boff[t];
-                uint64_t ne = est ? a.bcursor[t] : a.bcount[t];
-                if (est && ne > d.bcap)
-                    ne = d.bcap;  // overflowed slice: the job is run again exactly
-                for (uint64_t e = tid; e < ne; e += NT) {
-                    const uint32_t v = a.bdata[e0 + e];
-                    const uint32_t bit = v & 0x7FFFFFFFu;
-                    lds_or(((bit >> 3) & ~3u) + ((v >> 31) ? base5 : 0u), 1u << (bit & 31));
+            uint32_t *const g1 = a.gbm + ((uint64_t)d.gtile0 + k) * 2 * pw;
+            uint32_t *const g5 = g1 + pw;
+            // Four primes per thread per pass, their constants loaded
+            // together: the table of a high tile lies beyond L2, so the
+            // loads' latency, not the arithmetic, bounds this loop.
+            constexpr uint32_t kQ = 4;
+            for (uint32_t rb = r0 + tid; rb < r1; rb += kQ * NT) {
+                PrimeConst pcs[kQ];
+#pragma unroll
+                for (uint32_t q = 0; q < kQ; ++q)
+                    if (rb + q * NT < r1)
+                        pcs[q] = a.prm[a.k_split + rb + q * NT];
+#pragma unroll
+                for (uint32_t q = 0; q < kQ; ++q) {
+                    const PrimeConst &pc = pcs[q];
+                    if (rb + q * NT >= r1 || pc.p > sqe)
+                        continue;  // past the part, or P * P >= tile end
+                    uint32_t id1, id5;
+                    if (U24)
+                        tile_start_u24(pc, sqb, Bm1, B32, narrow, id1, id5);
+                    else
+                        tile_start(pc, sqb, Bm1, B32, narrow, id1, id5);
+                    // i < nbits < 2^20 and P < 2^32 - 2^20: i + P does not wrap
+                    for (uint32_t i = id1; i < nbits; i += pc.p)
+                        atomicOr(&g1[i >> 5], 1u << (i & 31));
+                    for (uint32_t i = id5; i < nbits; i += pc.p)
+                        atomicOr(&g5[i >> 5], 1u << (i & 31));
                 }
             }
         }
-        __syncthreads();
+
+        // ---- split tiles: the parts meet in the global planes; the
+        // workgroup that finishes the last part counts or lists the tile
+        if (split) {
+            uint32_t *const g1 = a.gbm + ((uint64_t)d.gtile0 + k) * 2 * pw;
+            if (part == 0)
+                for (uint32_t w = tid; w < nwords; w += NT) {
+                    if (pl1[w])
+                        atomicOr(&g1[w], pl1[w]);
+                    if (pl5[w])
+                        atomicOr(&g1[pw + w], pl5[w]);
+                }
+            __threadfence();  // this workgroup's marks are done before it arrives
+            __syncthreads();
+            if (tid == 0)
+                sh.last = atomicAdd(&a.garrive[(uint64_t)d.gtile0 + k], 1u) + 1u == d.nparts ? 1u : 0u;
+            __syncthreads();
+            if (sh.last == 0) {
+                __syncthreads();
+                continue;  // another part's workgroup finishes the tile
+            }
+            __threadfence();
+            for (uint32_t w = tid; w < nwords; w += NT) {
+                pl1[w] = __hip_atomic_load(&g1[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                pl5[w] = __hip_atomic_load(&g1[pw + w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            __syncthreads();
+        }
 
         // ---- edges, then count or bitmap ---------------------------------
         uint32_t head1 = 0, head5 = 0, tail1 = 0, tail5 = 0;
@@ -997,17 +1082,22 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(CompactArgs a)
 }
 
 __global__ void k_zero(const JobHeader *job, unsigned long long *counters, unsigned long long *counts,
-                       uint32_t *bcount)
+                       uint32_t *bcount, uint32_t *gbm, uint32_t *garrive)
 {
     const uint32_t n = job->nranges;
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t stride = gridDim.x * blockDim.x;
     if (g < kNumCounters)
         counters[g] = 0;
-    for (uint32_t i = g; i < n; i += gridDim.x * blockDim.x)
+    for (uint32_t i = g; i < n; i += stride)
         counts[i] = 0;
     if (job->nunits)
-        for (uint64_t i = g; i < job->ntiles; i += gridDim.x * blockDim.x)
+        for (uint64_t i = g; i < job->ntiles; i += stride)
             bcount[i] = 0;  // count (exact layout) or cursor (estimated layout)
+    for (uint64_t i = g; i < job->gwords; i += stride)
+        gbm[i] = 0;
+    for (uint64_t i = g; i < job->gtiles; i += stride)
+        garrive[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1028,9 +1118,9 @@ hipError_t set_sieve_lds_limit(uint32_t segment_bytes)
 }
 
 hipError_t launch_zero(const JobHeader *job, unsigned long long *counters, unsigned long long *counts,
-                       uint32_t *bcount, hipStream_t s)
+                       uint32_t *bcount, uint32_t *gbm, uint32_t *garrive, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_zero, dim3(256), dim3(256), 0, s, job, counters, counts, bcount);
+    hipLaunchKernelGGL(k_zero, dim3(256), dim3(256), 0, s, job, counters, counts, bcount, gbm, garrive);
     return hipGetLastError();
 }
 

@@ -93,6 +93,7 @@ struct sieve_ctx {
     sieve::rt::DevBuf<unsigned long long> d_chunk_vbase;
     sieve::rt::DevBuf<unsigned long long> d_chunk_off;
     sieve::rt::DevBuf<unsigned long long> d_seg_sum, d_seg_base;  // chunk-offset scan segments
+    sieve::rt::DevBuf<uint32_t> d_gbm, d_garrive;  // split tiles: global planes, arrival counts
     unsigned char *h_blob = nullptr;  // pinned staging for the blob
     size_t h_blob_n = 0;
     unsigned long long *h_counts = nullptr;  // pinned
@@ -104,7 +105,7 @@ struct sieve_ctx {
     sieve::rt::DevBuf<uint32_t> d_bcount, d_bcursor, d_bdata;
     sieve::rt::DevBuf<unsigned long long> d_boff;
     unsigned long long *h_btotal = nullptr;  // pinned
-    uint64_t cap_tiles = 0, cap_bdata = 0;
+    uint64_t cap_tiles = 0, cap_bdata = 0, cap_gtiles = 0;
 
     // Graphs of the job phases (0: whole job without buckets, 1: exact
     // bucket count + scan, 2: exact bucket fill + sieve + finalize + compact,

@@ -33,6 +33,7 @@ constexpr uint32_t kSegChunks = 4096;  // chunks per scan segment (4 per thread 
 constexpr uint32_t kBucketThreads = 512;    // primes per bucket work unit
 constexpr uint32_t kBucketWindow = 2048;    // tiles per bucket work unit (LDS bins)
 constexpr uint32_t kBucketMinPrimes = 32768; // fewest large primes worth a bucket pass
+constexpr uint32_t kPartPrimes = 262144;     // fewest primes (beyond the split items) per part of a split tile
 
 // One range of a job.  Host-computed plan; read-only on the device.
 struct RangeDesc {
@@ -55,7 +56,9 @@ struct RangeDesc {
     uint32_t bcap;       // estimated layout: entries reserved per tile
     uint32_t nseg;       // list ranges: scan segments of kSegChunks chunks
     uint32_t seg0;       // global index of the first segment (running count)
-    uint32_t pad;
+    uint32_t nparts;     // work units per tile: 1, or the parts of a split tile
+    uint32_t gtile0;     // split ranges: first global-bitmap slot (one per tile)
+    uint32_t part_primes;  // split ranges: primes beyond the split items per part
 };
 
 // Per-job scalars, in device memory so that a captured graph can be replayed
@@ -72,6 +75,9 @@ struct JobHeader {
     int32_t elem_bytes;  // 4 or 8
     int32_t pad;
     uint64_t nseg;       // scan segments over all list ranges
+    uint64_t nvisit;     // sieve work units: tiles times their parts, over all ranges
+    uint64_t gtiles;     // tiles of split ranges (global-bitmap slots)
+    uint64_t gwords;     // words of those slots (2 planes each)
 };
 
 // The order in which the sieve kernel's workgroups take tiles: ranges in
@@ -128,6 +134,8 @@ struct SieveArgs {
     const unsigned long long *boff;  // exact layout, per tile: first entry
     const uint32_t *bcount;       // exact layout, per tile: entries
     const uint32_t *bcursor;      // estimated layout, per tile: entries written
+    uint32_t *gbm;                // split tiles: both planes per slot (2 pw words), zeroed per job
+    uint32_t *garrive;            // split tiles: parts finished, per slot, zeroed per job
 };
 
 // Bucket sieve (large primes of multi-tile ranges).  One work unit is a block
