@@ -596,24 +596,35 @@ __device__ inline HitWalk walk_init(const BucketArgs &a, const RangeDesc &d, uin
     const PrimeConst pc = a.prm[k];
     const uint64_t P = pc.p;
     const uint64_t P2 = P * P;
-    const uint64_t wbase = d.base + (uint64_t)w0 * a.span;
-    const uint64_t M = P2 > wbase ? P2 : wbase;
+    const uint64_t wbase = d.base + (uint64_t)w0 * a.span;  // uniform
     const uint64_t rend = d.base + (uint64_t)wend * a.span;
-    if (M >= rend)
-        return w;
-    // tile holding M, by the reciprocal of the tile span
-    const uint64_t x = M - d.base;
-    uint64_t tM = mulhi64(x, a.span_rcp);
-    if (x - tM * a.span >= a.span)
-        ++tM;
-    const uint64_t Bt = d.base + tM * a.span;
-    uint32_t id1, id5;
     const uint32_t R = pc.r & 0x1FFFFFFFu, inv5 = pc.r >> 29;
-    // (M - 1) mod P: M is P^2 or the window base (the tile base Bt then)
-    const uint32_t rem = start_rem(pc, wbase, P2, rend <= (1ull << 62));
-    wheel_start(pc.p, R, Bt, M, rem, id1, id5);
+    uint32_t id1, id5, bt5;
+    uint64_t tM;
+    if (P2 <= wbase) {
+        // The usual case: the first value is the window base itself, so the
+        // walk starts in tile w0 with rem = (wbase - 1) mod P.
+        const uint64_t x = wbase - 1;
+        const uint32_t rem = rend <= (1ull << 62)
+                                 ? mod_narrow((uint32_t)x, (uint32_t)(x >> 32), pc.p, pc.m_lo, pc.m_hi & ~kP5Flag)
+                                 : mod_invariant(x, pc.p, prime_recip(pc), false);
+        wheel_start(pc.p, R, wbase, wbase, rem, id1, id5);
+        tM = w0;
+        bt5 = (uint32_t)(wbase % 5);
+    } else {
+        // P^2 lies beyond the window base: its tile, by the reciprocal of the
+        // tile span, and rem = (P^2 - 1) mod P = P - 1.
+        if (P2 >= rend)
+            return w;
+        const uint64_t x = P2 - d.base;
+        tM = mulhi64(x, a.span_rcp);
+        if (x - tM * a.span >= a.span)
+            ++tM;
+        const uint64_t Bt = d.base + tM * a.span;
+        wheel_start(pc.p, R, Bt, P2, pc.p - 1u, id1, id5);
+        bt5 = (uint32_t)(Bt % 5);
+    }
     if (a.skip5) {
-        const uint32_t bt5 = (uint32_t)(Bt % 5);
         w.c1 = cofactor_mod5(bt5, id1, 1, inv5);
         w.c5 = cofactor_mod5(bt5, id5, 0, inv5);
     }
@@ -652,13 +663,19 @@ __device__ inline uint32_t find_unit_range(const RangeDesc *ranges, uint32_t nra
 
 // LDS (dynamic, a.win bins): fill passes hold the 64-bit slice base of
 // every tile of the window, then the per-tile counts, which the fill walk
-// reuses as slot cursors.
+// reuses as slot cursors, then kBucketKeep hits per thread from the count
+// walk (window tile << 21 | plane << 20 | bit: the window has at most 2^11
+// tiles and a plane at most 2^20 bits), which the fill replays instead of
+// walking again when the thread had no more hits than that.
+static_assert(kBucketWindow <= (1u << 11), "kept hits hold the window tile in 11 bits");
+
 template <int PASS>
 __global__ void __launch_bounds__(kBucketThreads) k_bucket(BucketArgs a)
 {
     extern __shared__ unsigned long long s_bucket[];
     unsigned long long *s_base = s_bucket;
     uint32_t *s_cnt = (uint32_t *)(s_bucket + (PASS ? a.win : 0));
+    uint32_t *s_keep = s_cnt + a.win;  // fill passes: kBucketKeep x kBucketThreads
     const uint32_t tid = threadIdx.x;
     const uint64_t nunits = a.job->nunits;
     const uint32_t nranges = a.job->nranges;
@@ -698,16 +715,25 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket(BucketArgs a)
                 if (s_cnt[i])
                     atomicAdd(&a.bcount[d.tile0 + w0 + i], s_cnt[i]);
         } else {
+            uint32_t nk = 0;  // this thread's hits (the first kBucketKeep are kept)
             {
                 HitWalk c = w;  // count first, without moving the walk
                 while (c.t1 < wend) {
-                    if (c.c1)
+                    if (c.c1) {
                         atomicAdd(&s_cnt[c.t1 - w0], 1u);
+                        if (nk < kBucketKeep)
+                            s_keep[nk * kBucketThreads + tid] = ((c.t1 - w0) << 21) | c.b1;
+                        ++nk;
+                    }
                     walk_step(c.t1, c.b1, c.c1, c, nbits);
                 }
                 while (c.t5 < wend) {
-                    if (c.c5)
+                    if (c.c5) {
                         atomicAdd(&s_cnt[c.t5 - w0], 1u);
+                        if (nk < kBucketKeep)
+                            s_keep[nk * kBucketThreads + tid] = ((c.t5 - w0) << 21) | (1u << 20) | c.b5;
+                        ++nk;
+                    }
                     walk_step(c.t5, c.b5, c.c5, c, nbits);
                 }
             }
@@ -729,23 +755,35 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket(BucketArgs a)
                 }
             }
             __syncthreads();
-            while (w.t1 < wend) {
-                if (w.c1) {
-                    const uint32_t slot = atomicAdd(&s_cnt[w.t1 - w0], 1u);
-                    const unsigned long long b0 = s_base[w.t1 - w0];
+            if (nk <= kBucketKeep) {
+                // replay the kept hits
+                for (uint32_t i = 0; i < nk; ++i) {
+                    const uint32_t v = s_keep[i * kBucketThreads + tid];
+                    const uint32_t tw = v >> 21;
+                    const uint32_t slot = atomicAdd(&s_cnt[tw], 1u);
+                    const unsigned long long b0 = s_base[tw];
                     if (b0 != ~0ull)
-                        a.bdata[b0 + slot] = w.b1;
+                        a.bdata[b0 + slot] = (v & 0xFFFFFu) | ((v << 11) & 0x80000000u);
                 }
-                walk_step(w.t1, w.b1, w.c1, w, nbits);
-            }
-            while (w.t5 < wend) {
-                if (w.c5) {
-                    const uint32_t slot = atomicAdd(&s_cnt[w.t5 - w0], 1u);
-                    const unsigned long long b0 = s_base[w.t5 - w0];
-                    if (b0 != ~0ull)
-                        a.bdata[b0 + slot] = w.b5 | 0x80000000u;
+            } else {
+                while (w.t1 < wend) {
+                    if (w.c1) {
+                        const uint32_t slot = atomicAdd(&s_cnt[w.t1 - w0], 1u);
+                        const unsigned long long b0 = s_base[w.t1 - w0];
+                        if (b0 != ~0ull)
+                            a.bdata[b0 + slot] = w.b1;
+                    }
+                    walk_step(w.t1, w.b1, w.c1, w, nbits);
                 }
-                walk_step(w.t5, w.b5, w.c5, w, nbits);
+                while (w.t5 < wend) {
+                    if (w.c5) {
+                        const uint32_t slot = atomicAdd(&s_cnt[w.t5 - w0], 1u);
+                        const unsigned long long b0 = s_base[w.t5 - w0];
+                        if (b0 != ~0ull)
+                            a.bdata[b0 + slot] = w.b5 | 0x80000000u;
+                    }
+                    walk_step(w.t5, w.b5, w.c5, w, nbits);
+                }
             }
         }
         __syncthreads();
@@ -1146,7 +1184,9 @@ hipError_t launch_bucket(const BucketArgs &a, int pass, uint32_t cus, hipStream_
 {
     if (a.win < 1 || a.win > kBucketWindow || (a.win & (a.win - 1)))
         return hipErrorInvalidValue;
-    const size_t lds = (size_t)a.win * (pass ? sizeof(unsigned long long) + sizeof(uint32_t) : sizeof(uint32_t));
+    const size_t lds = pass ? (size_t)a.win * (sizeof(unsigned long long) + sizeof(uint32_t)) +
+                                  (size_t)kBucketKeep * kBucketThreads * sizeof(uint32_t)
+                            : (size_t)a.win * sizeof(uint32_t);
     // residency per (pass, power-of-two window): queried once
     static std::atomic<int> occ[3][16];
     int w2 = 0;

@@ -33,6 +33,7 @@ constexpr uint32_t kSegChunks = 4096;  // chunks per scan segment (4 per thread 
 constexpr uint32_t kBucketThreads = 512;    // primes per bucket work unit
 constexpr uint32_t kBucketWindow = 2048;    // tiles per bucket work unit (LDS bins)
 constexpr uint32_t kBucketMinPrimes = 32768; // fewest large primes worth a bucket pass
+constexpr uint32_t kBucketKeep = 4;          // hits per thread the bucket fill replays from LDS
 constexpr uint32_t kPartPrimes = 262144;     // fewest primes (beyond the split items) per part of a split tile
 
 // One range of a job.  Host-computed plan; read-only on the device.
