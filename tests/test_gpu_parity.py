@@ -219,6 +219,32 @@ def test_split_tiles_small_jobs(lo, hi, params):
         assert int(c[0]) == len(want) and int(c[2]) == len(want) and int(c[1]) == 4118054813
 
 
+def test_random_batch_to_1e15():
+    """Seeded uneven batch across nine decades: bucket ranges, split and
+    unsplit single tiles and long low ranges in one job, in the host's visit
+    order; counts and (for every other range) uint64 lists against the oracle."""
+    rng = np.random.default_rng(23)
+    n = 128
+    lo = np.floor(10 ** rng.uniform(6, 15, n)).astype(np.uint64)
+    hi = lo + np.floor(10 ** rng.uniform(3, 7, n)).astype(np.uint64)
+    mode = (np.arange(n) % 2).astype(np.uint8)
+    with pkg.Sieve(0) as s:
+        s.ensure_base_for(int(hi.max()))
+        want = [oracle.primes(int(a), int(b), elem_bytes=8, threads=4) for a, b in zip(lo, hi)]
+        assert np.array_equal(s.count_batch(lo, hi), np.array([len(w) for w in want], dtype=np.uint64))
+        cap = np.array([pkg.list_bound(int(a), int(b)) if m else 0 for a, b, m in zip(lo, hi, mode)],
+                       dtype=np.uint64)
+        off = np.concatenate([[0], np.cumsum(cap)[:-1]]).astype(np.uint64)
+        out = torch.zeros(int(cap.sum()) + 1, dtype=torch.int64, device="cuda")
+        counts, status = s.list_batch(lo, hi, mode, out, off, cap, elem_bytes=8)
+        host = _u(out, 8)
+        for i in range(n):
+            assert int(counts[i]) == len(want[i]) and status[i] == 0, (int(lo[i]), int(hi[i]))
+            if mode[i]:
+                o = int(off[i])
+                assert np.array_equal(host[o:o + len(want[i])], want[i]), (int(lo[i]), int(hi[i]))
+
+
 def test_capacity_error_reports_count(sv):
     n_true = oracle.count(10 ** 6, 2 * 10 ** 6)
     out = torch.empty(10, dtype=torch.int64, device="cuda")
