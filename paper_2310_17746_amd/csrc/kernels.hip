@@ -1029,7 +1029,9 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(CompactArgs a)
 {
     constexpr uint32_t kW = kCompactThreads / kWave;
     constexpr uint32_t kU = 2;  // contiguous chunks per workgroup iteration
-    __shared__ T s_stage[kW][kStagePerWave];  // one staging window per wavefront
+    // one staging window per wavefront: value offsets from the chunk's value
+    // base (below kChunkVals, so 32 bits suffice for either element type)
+    __shared__ uint32_t s_stage[kW][kStagePerWave];
     __shared__ uint32_t s_wt[2][kW];              // per-wave totals, alternating per chunk
     __shared__ unsigned long long s_meta[2][kU];  // output offset, value base
     const uint32_t tid = threadIdx.x;
@@ -1093,26 +1095,51 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(CompactArgs a)
                 woff += q < wave ? wt[q] : 0u;
             const uint32_t wtot = wt[wave];
             const uint64_t obase = coff + woff;
-            const uint64_t vb = s_meta[1][u] + kValsPerWord * tid;
+            const uint64_t cvb = s_meta[1][u];        // value base of the chunk (uniform)
+            const uint32_t tb = kValsPerWord * tid;   // this word's offset in the chunk
             const uint32_t excl = incl - cnt;
-            // Passes over rank windows of kStagePerWave, uniform across the wavefront.
-            for (uint32_t pass = 0; pass < wtot; pass += kStagePerWave) {
-                if (excl < pass + kStagePerWave && excl + cnt > pass) {
-                    uint64_t mm = m;
-                    uint32_t pos = excl;
-                    while (mm) {
-                        const uint32_t b = (uint32_t)__builtin_ctzll(mm);
-                        mm &= mm - 1;
-                        if (pos >= pass && pos < pass + kStagePerWave)
-                            s_stage[wave][pos - pass] = (T)(vb + 3ull * b + 1ull + (b & 1u));
-                        ++pos;
-                    }
+            // Bit b of the word (bit 2i <-> 6i + 1, bit 2i + 1 <-> 6i + 5) is the
+            // value tb + 3b + 1 + (b & 1) past the chunk base.
+            if (wtot <= kStagePerWave) {
+                // the usual case: the wave's primes fit one staging window;
+                // the word's halves are walked with 32-bit operations
+                uint32_t pos = excl;
+                uint32_t h = (uint32_t)m;
+                while (h) {
+                    const uint32_t b = (uint32_t)__builtin_ctz(h);
+                    h &= h - 1;
+                    s_stage[wave][pos++] = tb + 3u * b + 1u + (b & 1u);
+                }
+                h = (uint32_t)(m >> 32);
+                while (h) {
+                    const uint32_t b = 32u + (uint32_t)__builtin_ctz(h);
+                    h &= h - 1;
+                    s_stage[wave][pos++] = tb + 3u * b + 1u + (b & 1u);
                 }
                 wave_lds_fence();  // the window is written before any lane reads it
-                const uint32_t n_in = (wtot - pass) < kStagePerWave ? (wtot - pass) : kStagePerWave;
-                for (uint32_t e = lane; e < n_in; e += kWave)
-                    out[obase + pass + e] = s_stage[wave][e];
-                wave_lds_fence();  // and read before the next pass rewrites it
+                for (uint32_t e = lane; e < wtot; e += kWave)
+                    out[obase + e] = (T)(cvb + s_stage[wave][e]);
+                wave_lds_fence();  // and read before the next chunk rewrites it
+            } else {
+                // Passes over rank windows of kStagePerWave, uniform across the wavefront.
+                for (uint32_t pass = 0; pass < wtot; pass += kStagePerWave) {
+                    if (excl < pass + kStagePerWave && excl + cnt > pass) {
+                        uint64_t mm = m;
+                        uint32_t pos = excl;
+                        while (mm) {
+                            const uint32_t b = (uint32_t)__builtin_ctzll(mm);
+                            mm &= mm - 1;
+                            if (pos >= pass && pos < pass + kStagePerWave)
+                                s_stage[wave][pos - pass] = tb + 3u * b + 1u + (b & 1u);
+                            ++pos;
+                        }
+                    }
+                    wave_lds_fence();
+                    const uint32_t n_in = (wtot - pass) < kStagePerWave ? (wtot - pass) : kStagePerWave;
+                    for (uint32_t e = lane; e < n_in; e += kWave)
+                        out[obase + pass + e] = (T)(cvb + s_stage[wave][e]);
+                    wave_lds_fence();
+                }
             }
         }
         lds_barrier();  // s_meta is rewritten by the next iteration
