@@ -25,7 +25,8 @@ host threads) timed on a bounded slice of the same workload.
 * batch_4096: the 4096 seeded uneven ranges (half listed as uint64) in one
   batched call replaying a captured graph, against the same ranges as one
   plain call each; primes/s counts every prime counted or listed.  Its launch
-  parameters come from the autotuner run on a 1024-range sample first.
+  parameters come from the autotuner, run first on the same 4096 ranges
+  (counted).
 * serve_2000: 2000 seeded requests with Poisson arrivals at 0.8 x the
   saturated request rate (measured first with all requests at t = 0) and the
   count of [2, 10^12] submitted at t = 0; p50/p99 of completion - arrival.
