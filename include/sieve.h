@@ -318,7 +318,7 @@ typedef struct sieve_server sieve_server;
 typedef struct sieve_server_params {
     uint64_t out_budget_bytes; /* device output arena; default 1 GiB */
     uint32_t max_active;       /* requests on the device at once; default 1024 */
-    uint32_t step_tiles;       /* tiles per scheduler step; default 8 per CU */
+    uint32_t step_tiles;       /* tiles per scheduler step; default 16 per CU */
     uint32_t quantum_tiles;    /* tiles per request per step; default step_tiles / 8 */
     uint32_t elem_bytes;       /* list element size, 4 or 8; default 8 */
     uint32_t max_queue;        /* submitted but not admitted; default 1 << 20 */

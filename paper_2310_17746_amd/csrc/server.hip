@@ -342,7 +342,7 @@ int sieve_server_create(sieve_ctx *ctx, const sieve_server_params *p, sieve_serv
     if (!q.max_active)
         q.max_active = 1024;
     if (!q.step_tiles)
-        q.step_tiles = 8u * (uint32_t)ctx->cus;
+        q.step_tiles = 16u * (uint32_t)ctx->cus;
     if (!q.quantum_tiles)
         q.quantum_tiles = std::max<uint32_t>(1, q.step_tiles / 8);
     if (!q.elem_bytes)
