@@ -336,6 +336,74 @@ def bench_serve(pkg, workloads):
             "steps": st["steps"]}
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_other_workloads(oracle, threads):
+    """The oracle on bounded samples of configs 1, 2, 4 and 5 and of the
+    window list, on `threads` threads and (on a smaller sample) on one."""
+    from paper_2310_17746_amd import workloads as wl
+    blo, bhi, _ = wl.batch_ranges(0)
+    bsel = np.random.default_rng(3).choice(len(blo), 64, replace=False)
+    slo, shi, smode, _ = wl.serving_requests(1)
+    short = np.nonzero(shi - slo <= 10 ** 8)[0]
+    ssel = np.random.default_rng(4).choice(short, 32, replace=False)
+
+    def batch(sel, th):
+        return sum(oracle.count(int(blo[i]), int(bhi[i]), threads=th) for i in sel)
+
+    def serve(sel, th):
+        n = 0
+        for i in sel:
+            if smode[i]:
+                n += len(oracle.primes(int(slo[i]), int(shi[i]), elem_bytes=8, threads=th))
+            else:
+                n += oracle.count(int(slo[i]), int(shi[i]), threads=th)
+        return n
+
+    def lst(lo, hi, eb):
+        return lambda th: len(oracle.primes(lo, hi, elem_bytes=eb, threads=th))
+
+    # name: (all-threads sample, its integers, its call), (one-thread sample, integers, call)
+    cases = {
+        "config1_list": (("[2, 10^7 + 1) listed as uint32", 10 ** 7 - 1, lst(2, 10 ** 7 + 1, 4)),
+                         ("the same", 10 ** 7 - 1, lst(2, 10 ** 7 + 1, 4))),
+        "config2_list": (("[2, 10^9 + 1) listed as uint32", 10 ** 9 - 1, lst(2, 10 ** 9 + 1, 4)),
+                         ("[2, 10^8 + 1) listed as uint32", 10 ** 8 - 1, lst(2, 10 ** 8 + 1, 4))),
+        "list_window_sample": (("[10^12, 10^12 + 10^8) listed as uint64", 10 ** 8,
+                                lst(10 ** 12, 10 ** 12 + 10 ** 8, 8)),
+                               ("[10^12, 10^12 + 2 10^7) listed as uint64", 2 * 10 ** 7,
+                                lst(10 ** 12, 10 ** 12 + 2 * 10 ** 7, 8))),
+        "batch_sample": (("64 of the 4096 config-4 ranges, counted", int((bhi[bsel] - blo[bsel]).sum()),
+                          lambda th: batch(bsel, th)),
+                         ("16 of those 64", int((bhi[bsel[:16]] - blo[bsel[:16]]).sum()),
+                          lambda th: batch(bsel[:16], th))),
+        "serve_sample": (("32 of the config-5 requests of at most 10^8 integers (counted or listed as uint64)",
+                          int((shi[ssel] - slo[ssel]).sum()), lambda th: serve(ssel, th)),
+                         ("8 of those 32", int((shi[ssel[:8]] - slo[ssel[:8]]).sum()),
+                          lambda th: serve(ssel[:8], th))),
+    }
+    out = {}
+    for name, (full, small) in cases.items():
+        r = {}
+        for tag, th, (sample, ints, fn) in (("all_threads", threads, full), ("one_thread", 1, small)):
+            t0 = time.perf_counter()
+            primes = fn(th)
+            dt = time.perf_counter() - t0
+            r[tag] = {"sample": sample, "ms": round(dt * 1e3, 1), "ints_per_s": round(ints / dt, 1),
+                      "primes_per_s": round(primes / dt, 1)}
+        out[name] = r
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -351,6 +419,8 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true", help="headline count only")
     ap.add_argument("--cpu-sample", type=int, default=10 ** 11,
                     help="integers of the oracle's timed slice (the top of the range)")
+    ap.add_argument("--extra", default="", choices=["", "list_1e9", "list_window", "batch_4096", "serve_2000"],
+                    help="run only this extra workload and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (5 times), the reference "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -381,6 +451,14 @@ def main() -> int:
     params = {k: v for k, v in dict(segment_bytes=args.segment_bytes, block_threads=args.block_threads,
                                      wg_per_cu=args.wg_per_cu, split_hits=args.split_hits,
                                      presieve_groups=args.presieve_groups).items() if v}
+    if args.extra:
+        from paper_2310_17746_amd import workloads
+        fn = {"list_1e9": lambda: bench_list(pkg, torch, params),
+              "list_window": lambda: bench_list_window(pkg, torch, params),
+              "batch_4096": lambda: bench_batch(pkg, torch, params, workloads),
+              "serve_2000": lambda: bench_serve(pkg, workloads)}[args.extra]
+        print(json.dumps({"extra": args.extra, **fn()}), flush=True)
+        return 0
     s = pkg.Sieve(0, params)
     s.ensure_base_for(hi)                     # base primes resident before timing
     prm = s.params.as_dict()
@@ -425,6 +503,15 @@ def main() -> int:
                           "frac_conflict_free": round(achieved / probe["or_linear"], 4),
                           "random_words": round(probe["or_random"], 1),
                           "frac_random_words": round(achieved / probe["or_random"], 4)}
+    if tr and "lds_counter_bytes" in tr:
+        # LDS bytes by the SQ_INSTS_LDS_*_BANDWIDTH counters (64-byte units) of
+        # the committed summary, over this run's kernel time
+        cb = tr["lds_counter_bytes"] / (k_ms * 1e-3) / 1e9
+        roof["lds_counter"] = {"bytes": int(tr["lds_counter_bytes"]), "GB_per_s": round(cb, 1),
+                               "frac_conflict_free": round(cb / probe["or_linear"], 4),
+                               "frac_random_words": round(cb / probe["or_random"], 4),
+                               "frac_nominal": round(cb / roof["peak"], 4),
+                               "valu_per_mark": round(tr["valu_per_mark"], 2)}
 
     s.close()
     extras = None
@@ -458,25 +545,10 @@ def main() -> int:
         cpu = {"value": round((hi - a) / (t3 - t2), 1), "unit": "ints/s", "cores": th, "kind": "oracle",
                "sample": "oracle count of [%d, %d) (%d integers, the top of the workload): %d primes in %.2f s"
                          % (a, hi, hi - a, oc, t3 - t2)}
-        # the oracle on the other workloads (context for the extras; bounded samples)
-        t6 = time.perf_counter()
-        n2 = len(oracle.primes(2, 10 ** 9 + 1, elem_bytes=4, threads=th))
-        t7 = time.perf_counter()
-        n3 = len(oracle.primes(10 ** 12, 10 ** 12 + 10 ** 9, elem_bytes=8, threads=th))
-        t8 = time.perf_counter()
-        from paper_2310_17746_amd import workloads as _wl
-        blo, bhi, _ = _wl.batch_ranges(0)
-        sel = np.random.default_rng(3).choice(len(blo), 64, replace=False)
-        bints = int((bhi[sel] - blo[sel]).sum())
-        for a_, b_ in zip(blo[sel].tolist(), bhi[sel].tolist()):
-            oracle.count(a_, b_, threads=th)
-        t9 = time.perf_counter()
-        cpu["other_workloads"] = {
-            "list_1e9": {"primes_per_s": round(n2 / (t7 - t6), 1), "ms": round((t7 - t6) * 1e3, 1)},
-            "list_window_sample": {"sample": "[10^12, 10^12 + 10^9)", "primes_per_s": round(n3 / (t8 - t7), 1),
-                                   "ms": round((t8 - t7) * 1e3, 1)},
-            "batch_sample": {"sample": "64 of the 4096 ranges, counted", "ints_per_s": round(bints / (t9 - t8), 1),
-                             "ms": round((t9 - t8) * 1e3, 1)}}
+        # the oracle on the other workloads (context for the extras; bounded
+        # samples), on all threads and on one
+        cpu["cpu_model"] = cpu_model()
+        cpu["other_workloads"] = oracle_other_workloads(oracle, th)
         # the same oracle on one thread, over the top 10^9 integers of the workload
         a1 = max(lo, hi - 10 ** 9)
         t4 = time.perf_counter()
