@@ -103,6 +103,12 @@ typedef struct sieve_ctx sieve_ctx;
  *                    MiB (default 4096).  A job whose estimate is larger runs
  *                    as a sequence of jobs over tile-aligned pieces of its
  *                    ranges; results are the same.
+ *   visit_order      order in which the sieve kernel's workgroups take the
+ *                    ranges' tiles: SIEVE_VISIT_COSTLY_FIRST (0, default:
+ *                    most Table 1 starts per tile first), SIEVE_VISIT_REVERSED
+ *                    (that order reversed) or SIEVE_VISIT_SHUFFLED (a fixed
+ *                    pseudo-random permutation of the ranges).  Results do not
+ *                    depend on it; the other two exist for testing.
  */
 typedef struct sieve_params {
     uint32_t segment_bytes;
@@ -116,7 +122,8 @@ typedef struct sieve_params {
     uint32_t cofactor_skip;
     uint32_t bucket_mem_mb;
     uint32_t dense_hits;
-    uint32_t reserved[5];
+    uint32_t visit_order;
+    uint32_t reserved[4];
 } sieve_params;
 
 #define SIEVE_PRESIEVE_NONE 0xFFFFFFFFu
@@ -127,6 +134,9 @@ typedef struct sieve_params {
 #define SIEVE_SKIP_NONE 2u
 #define SIEVE_SKIP_SPLIT 3u
 #define SIEVE_DENSE_NEVER 0xFFFFFFFFu
+#define SIEVE_VISIT_COSTLY_FIRST 0u
+#define SIEVE_VISIT_REVERSED 1u
+#define SIEVE_VISIT_SHUFFLED 2u
 
 /* Fills *p with the library defaults for gfx950. */
 int sieve_default_params(sieve_params *p);

@@ -44,6 +44,7 @@ SKIP_ALL = 1
 SKIP_NONE = 2
 SKIP_SPLIT = 3
 DENSE_NEVER = 0xFFFFFFFF
+VISIT_COSTLY_FIRST, VISIT_REVERSED, VISIT_SHUFFLED = 0, 1, 2
 
 _u64 = ctypes.c_uint64
 _p = ctypes.c_void_p
@@ -56,7 +57,8 @@ class Params(ctypes.Structure):
                 ("bucket_threshold", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32),
                 ("use_graph", ctypes.c_uint32), ("bucket_slices", ctypes.c_uint32),
                 ("cofactor_skip", ctypes.c_uint32), ("bucket_mem_mb", ctypes.c_uint32),
-                ("dense_hits", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 5)]
+                ("dense_hits", ctypes.c_uint32), ("visit_order", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 4)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

@@ -129,6 +129,8 @@ int validate_params(const sieve_params &p, uint32_t lds_max)
         return SIEVE_E_INVAL;
     if (p.bucket_slices > SIEVE_BUCKET_TINY || p.cofactor_skip > SIEVE_SKIP_SPLIT)
         return SIEVE_E_INVAL;
+    if (p.visit_order > SIEVE_VISIT_SHUFFLED)
+        return SIEVE_E_INVAL;
     return SIEVE_OK;
 }
 
@@ -725,6 +727,16 @@ int run_job_once(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *h
             key[i] = d.nparts > 1 ? d.part_primes : std::min(d.nact, d.kbig);
         }
         std::stable_sort(ord.begin(), ord.end(), [&](uint32_t x, uint32_t y) { return key[x] > key[y]; });
+        if (c->prm.visit_order == SIEVE_VISIT_REVERSED) {
+            std::reverse(ord.begin(), ord.end());
+        } else if (c->prm.visit_order == SIEVE_VISIT_SHUFFLED) {
+            // Fisher-Yates with a fixed 64-bit LCG (Knuth's MMIX constants)
+            uint64_t x = 0x9E3779B97F4A7C15ull;
+            for (uint64_t i = n; i > 1; --i) {
+                x = x * 6364136223846793005ull + 1442695040888963407ull;
+                std::swap(ord[i - 1], ord[(x >> 33) % i]);
+            }
+        }
         VisitEntry *v = (VisitEntry *)(c->h_blob + L.visit);
         uint64_t pos = 0;
         for (uint64_t j = 0; j < n; ++j) {
