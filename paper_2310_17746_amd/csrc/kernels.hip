@@ -1032,8 +1032,10 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(CompactArgs a)
     // one staging window per wavefront: value offsets from the chunk's value
     // base (below kChunkVals, so 32 bits suffice for either element type)
     __shared__ uint32_t s_stage[kW][kStagePerWave];
-    __shared__ uint32_t s_wt[2][kW];              // per-wave totals, alternating per chunk
-    __shared__ unsigned long long s_meta[2][kU];  // output offset, value base
+    // per iteration parity: per-wave totals of each chunk, and each chunk's
+    // output offset and value base
+    __shared__ uint32_t s_wt[2][kU][kW];
+    __shared__ unsigned long long s_meta[2][2][kU];
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1);
     const uint32_t wave = tid / kWave;
@@ -1052,14 +1054,15 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(CompactArgs a)
 
     // Each iteration takes kU contiguous chunks.  Their loads are issued
     // together at the top; the stores of all kU chunks stay in flight until
-    // the next iteration's loads are waited for.  Per chunk, the only
-    // workgroup barrier is the exchange of the per-wave totals; staging and
-    // storing touch only the wave's own window.  The totals alternate between
-    // two buffers per processed chunk: a wave writes a buffer again only after
-    // the barrier of the chunk in between, which every wave reaches after it
-    // has read that buffer.
-    uint32_t par = 0;
-    for (uint64_t c0 = (uint64_t)blockIdx.x * kU; c0 < nchunks; c0 += (uint64_t)gridDim.x * kU) {
+    // the next iteration's loads are waited for.  The wavefront scans of all
+    // kU chunks come first and one workgroup barrier then publishes every
+    // per-wave total; staging and storing touch only the wave's own window.
+    // The totals and the chunk metadata alternate between two buffers by
+    // iteration: a buffer is written again two iterations later, after the
+    // barrier of the iteration in between, which every wave reaches only
+    // after it has read that buffer.
+    uint32_t ip = 0;
+    for (uint64_t c0 = (uint64_t)blockIdx.x * kU; c0 < nchunks; c0 += (uint64_t)gridDim.x * kU, ip ^= 1u) {
         uint64_t mu[kU];
 #pragma unroll
         for (uint32_t u = 0; u < kU; ++u)
@@ -1067,8 +1070,8 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(CompactArgs a)
         if (tid < kU) {
             const uint64_t c = c0 + tid;
             // ~0: past the end, or the range does not fit (nothing is written)
-            s_meta[0][tid] = c < nchunks ? a.chunk_off[c] : ~0ull;
-            s_meta[1][tid] = c < nchunks ? a.chunk_vbase[c] : 0ull;
+            s_meta[ip][0][tid] = c < nchunks ? a.chunk_off[c] : ~0ull;
+            s_meta[ip][1][tid] = c < nchunks ? a.chunk_vbase[c] : 0ull;
         }
         // Consume the bitmap words here, before any store of this iteration:
         // the vector memory counter completes in order, so a later wait for
@@ -1076,26 +1079,30 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(CompactArgs a)
 #pragma unroll
         for (uint32_t u = 0; u < kU; ++u)
             asm volatile("" : "+v"(mu[u]));
+        uint32_t cnts[kU], incls[kU];
+#pragma unroll
+        for (uint32_t u = 0; u < kU; ++u) {
+            cnts[u] = __popcll(mu[u]);
+            incls[u] = wave_incl_scan(cnts[u], lane);
+            if (lane == kWave - 1)
+                s_wt[ip][u][wave] = incls[u];
+        }
         lds_barrier();
 #pragma unroll
         for (uint32_t u = 0; u < kU; ++u) {
-            const uint64_t coff = s_meta[0][u];
+            const uint64_t coff = s_meta[ip][0][u];
             if (coff == ~0ull)
                 continue;  // the same for every thread of the block
             const uint64_t m = mu[u];
-            const uint32_t cnt = __popcll(m);
-            const uint32_t incl = wave_incl_scan(cnt, lane);
-            uint32_t *const wt = s_wt[par];
-            par ^= 1u;
-            if (lane == kWave - 1)
-                wt[wave] = incl;
-            lds_barrier();
+            const uint32_t cnt = cnts[u];
+            const uint32_t incl = incls[u];
+            const uint32_t *const wt = s_wt[ip][u];
             uint32_t woff = 0;
             for (uint32_t q = 0; q < kW; ++q)
                 woff += q < wave ? wt[q] : 0u;
             const uint32_t wtot = wt[wave];
             const uint64_t obase = coff + woff;
-            const uint64_t cvb = s_meta[1][u];        // value base of the chunk (uniform)
+            const uint64_t cvb = s_meta[ip][1][u];    // value base of the chunk (uniform)
             const uint32_t tb = kValsPerWord * tid;   // this word's offset in the chunk
             const uint32_t excl = incl - cnt;
             // Bit b of the word (bit 2i <-> 6i + 1, bit 2i + 1 <-> 6i + 5) is the
@@ -1142,7 +1149,6 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(CompactArgs a)
                 }
             }
         }
-        lds_barrier();  // s_meta is rewritten by the next iteration
     }
 }
 
