@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 from oracle import brute
-from conftest import read_golden
+from conftest import assert_same_primes, read_golden
 
 pytestmark = pytest.mark.gpu
 
@@ -63,7 +63,7 @@ def test_count_tiny_ranges_exhaustive(sv):
 def test_list_small_u32(sv, lo, hi):
     got = _u(sv.list(lo, hi, elem_bytes=4), 4)
     want = oracle.primes(lo, hi, elem_bytes=4)
-    assert np.array_equal(got, want)
+    assert_same_primes(got, want)
 
 
 def test_list_random_windows_ragged(sv):
@@ -78,7 +78,7 @@ def test_list_random_windows_ragged(sv):
         sv.ensure_base_for(hi)
         got = _u(sv.list(lo, hi, elem_bytes=8), 8)
         want = oracle.primes(lo, hi, elem_bytes=8)
-        assert np.array_equal(got, want), (lo, hi)
+        assert_same_primes(got, want, (lo, hi))
         assert sv.count(lo, hi) == len(want), (lo, hi)
 
 
@@ -88,7 +88,7 @@ def test_config1_full_list(sv, pi_tab):
     got = _u(sv.list(lo, hi, elem_bytes=4), 4)
     want = oracle.primes(lo, hi, elem_bytes=4)
     assert len(got) == pi_tab[10 ** 7]
-    assert np.array_equal(got, want)
+    assert_same_primes(got, want)
 
 
 def test_config2_full_list(sv, pi_tab):
@@ -98,7 +98,7 @@ def test_config2_full_list(sv, pi_tab):
     got = _u(sv.list(lo, hi, elem_bytes=4), 4)
     want = oracle.primes(lo, hi, elem_bytes=4)
     assert len(got) == pi_tab[10 ** 9]
-    assert np.array_equal(got, want)
+    assert_same_primes(got, want)
 
 
 def test_pi_1e10_and_1e11_counts(sv, pi_tab):
@@ -120,7 +120,7 @@ def test_large_windows_vs_oracle(sv):
         sv.ensure_base_for(hi)
         got = _u(sv.list(lo, hi, elem_bytes=8), 8)
         want = oracle.primes(lo, hi, elem_bytes=8)
-        assert np.array_equal(got, want), lo
+        assert_same_primes(got, want, lo)
         # sampled Miller-Rabin on a few hundred listed values
         for v in got[:: max(1, len(got) // 200)].tolist():
             assert brute.is_prime_mr(int(v))
@@ -135,7 +135,7 @@ def test_count_batch_uneven(sv):
     sv.ensure_base_for(int(hi.max()))
     got = sv.count_batch(lo, hi)
     want = np.array([oracle.count(int(a), int(b), threads=4) for a, b in zip(lo, hi)], dtype=np.uint64)
-    assert np.array_equal(got, want)
+    assert_same_primes(got, want)
     # the same ranges alone give the same counts
     for i in range(0, n, 37):
         assert sv.count(int(lo[i]), int(hi[i])) == int(want[i])
@@ -210,7 +210,7 @@ def test_split_tiles_small_jobs(lo, hi, params):
         want = oracle.primes(lo, hi, elem_bytes=8, threads=4)
         assert s.count(lo, hi) == len(want)
         got = _u(s.list(lo, hi, elem_bytes=8), 8)
-        assert np.array_equal(got, want)
+        assert_same_primes(got, want)
         # inside a job whose share per workgroup is larger (pi(10^11): about
         # 2.8M starts per workgroup) the range is not split; counts agree
         los = np.array([lo, 2, lo], dtype=np.uint64)
@@ -296,7 +296,7 @@ def test_parameter_grid_parity(params):
         for lo, hi in [(0, 3 * 10 ** 7 + 17), (10 ** 11 - 5 * 10 ** 6, 10 ** 11 + 7 * 10 ** 6)]:
             got = _u(s.list(lo, hi, elem_bytes=8), 8)
             want = oracle.primes(lo, hi, elem_bytes=8)
-            assert np.array_equal(got, want), (params, lo, hi)
+            assert_same_primes(got, want, (params, lo, hi))
             assert s.count(lo, hi) == len(want)
 
 

@@ -148,3 +148,11 @@ def test_table1_remainder_edges():
             assert got == want, (P, base, M)
             n += 1
     assert n > 1000
+
+
+
+def test_first_mismatch_helper():
+    from conftest import first_mismatch
+    assert first_mismatch([2, 3, 5], [2, 3, 5]) is None
+    assert first_mismatch([2, 3, 7, 11], [2, 3, 5, 7])[0] == 2
+    assert first_mismatch([2, 3], [2, 3, 5]) == (2, [2, 3], [2, 3, 5])
