@@ -79,24 +79,22 @@ def lds_work(lo: int, hi: int, segment_bytes: int) -> tuple[int, int]:
     Primes 5..61 are presieved; every other base prime p marks p*m for the
     cofactors m coprime to 30 (multiples of 2, 3 are outside the wheel and
     multiples of 5 are already cleared by the presieve)."""
-    pw = segment_bytes // 8
     base = lo - lo % 6
     n1 = (hi - base - 1 + 5) // 6
     words = (n1 + 31) // 32
     end = base + 192 * words
     p = small_primes(math.isqrt(hi - 1))
     p = p[p > 61]                                  # 5..61 are presieved by patterns
-    ntiles = (words + pw - 1) // pw
-    tile_span = 192 * pw
-    marks = 0
-    # per tile the start is max(p^2, tile base); sum over tiles = over the span
-    # with the p^2 clamp, since tiles are contiguous
+    # per tile the start is max(p^2, tile base); the sum over the tiles is the
+    # sum over the whole span with the p^2 clamp, since tiles are contiguous
+    # (the tile size only sets where they meet: segment_bytes does not change
+    # the total)
+    del segment_bytes
     start = np.maximum(p * p, base)
     m_lo = -(-start // p)
     m_hi = (end - 1) // p
     ok = m_hi >= m_lo
     marks = int(np.sum(np.where(ok, coprime30_upto(m_hi) - coprime30_upto(m_lo - 1), 0)))
-    del ntiles, tile_span
     return marks, int(words)
 
 

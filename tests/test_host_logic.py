@@ -7,6 +7,7 @@
 * The tile planner covers every wheel value of a range exactly once.
 * sieve_list_bound is an upper bound on the oracle's counts.
 """
+import math
 import os
 import random
 import re
@@ -156,3 +157,25 @@ def test_first_mismatch_helper():
     assert first_mismatch([2, 3, 5], [2, 3, 5]) is None
     assert first_mismatch([2, 3, 7, 11], [2, 3, 5, 7])[0] == 2
     assert first_mismatch([2, 3], [2, 3, 5]) == (2, [2, 3], [2, 3, 5])
+
+
+def test_bench_mark_count_against_brute_force():
+    # the roofline's algorithmic LDS work: multiples p*m of every base prime
+    # p > 61 from max(p^2, base) to the end of the last plane word, with m
+    # coprime to 30 (2 and 3 are off the wheel, 5 is presieved)
+    import bench
+    rng = random.Random(12)
+    for _ in range(60):
+        lo = rng.randrange(0, 3 * 10 ** 5)
+        hi = lo + rng.randrange(1, 2 * 10 ** 4)
+        marks, words = bench.lds_work(lo, hi, 53248)
+        base = lo - lo % 6
+        end = base + 192 * words
+        want = 0
+        for p in range(67, math.isqrt(hi - 1) + 1):
+            if all(p % q for q in range(2, math.isqrt(p) + 1)):
+                for v in range(max(p * p, base), end):
+                    if v % p == 0 and math.gcd(v // p, 30) == 1:
+                        want += 1
+        assert marks == want, (lo, hi)
+        assert words == (((hi - base - 1 + 5) // 6) + 31) // 32
