@@ -126,7 +126,7 @@ def measured_traffic():
 
 
 def bench_list(pkg, torch, params, steps=5):
-    """Config 2: sorted uint32 list of the primes in [2, 10^9]."""
+    """Sorted uint32 list of the primes in [2, 10^9]."""
     lo, hi = 2, 10 ** 9 + 1
     s = pkg.Sieve(0, params)
     s.ensure_base_for(hi)
@@ -155,7 +155,7 @@ def bench_list(pkg, torch, params, steps=5):
 
 
 def bench_list_window(pkg, torch, params, steps=3):
-    """Config 3 window: sorted uint64 list of the primes in [10^12, 10^12 + 10^10)."""
+    """Sorted uint64 list of the primes in the window [10^12, 10^12 + 10^10)."""
     lo, hi = 10 ** 12, 10 ** 12 + 10 ** 10
     s = pkg.Sieve(0, params)
     s.ensure_base_for(hi)
@@ -212,7 +212,7 @@ def bench_cold(pkg, torch, params, hi=10 ** 11 + 1):
 
 
 def bench_batch(pkg, torch, params, workloads, steps=3):
-    """Config 4: 4096 seeded uneven ranges, half listed as uint64."""
+    """4096 seeded uneven ranges (seed 0, lo up to 10^15), half listed as uint64."""
     lo, hi, mode = workloads.batch_ranges(0)
     s = pkg.Sieve(0, dict(params, use_graph=1))
     s.ensure_base_for(int(hi.max()))
@@ -282,7 +282,7 @@ def bench_stream(pkg, torch, params):
 
 
 def bench_serve(pkg, workloads):
-    """Config 5: Poisson request stream with the [2, 10^12] count job beside it."""
+    """2000 seeded requests (seed 1) on a Poisson stream, with the [2, 10^12] count job beside it."""
     lo, hi, mode, gaps = workloads.serving_requests(1)
     long_lo, long_hi = workloads.LONG_JOB
     s = pkg.Sieve(0)
@@ -372,19 +372,19 @@ def oracle_other_workloads(oracle, threads):
 
     # name: (all-threads sample, its integers, its call), (one-thread sample, integers, call)
     cases = {
-        "config1_list": (("[2, 10^7 + 1) listed as uint32", 10 ** 7 - 1, lst(2, 10 ** 7 + 1, 4)),
+        "list_1e7": (("[2, 10^7 + 1) listed as uint32", 10 ** 7 - 1, lst(2, 10 ** 7 + 1, 4)),
                          ("the same", 10 ** 7 - 1, lst(2, 10 ** 7 + 1, 4))),
-        "config2_list": (("[2, 10^9 + 1) listed as uint32", 10 ** 9 - 1, lst(2, 10 ** 9 + 1, 4)),
+        "list_1e9": (("[2, 10^9 + 1) listed as uint32", 10 ** 9 - 1, lst(2, 10 ** 9 + 1, 4)),
                          ("[2, 10^8 + 1) listed as uint32", 10 ** 8 - 1, lst(2, 10 ** 8 + 1, 4))),
         "list_window_sample": (("[10^12, 10^12 + 10^8) listed as uint64", 10 ** 8,
                                 lst(10 ** 12, 10 ** 12 + 10 ** 8, 8)),
                                ("[10^12, 10^12 + 2 10^7) listed as uint64", 2 * 10 ** 7,
                                 lst(10 ** 12, 10 ** 12 + 2 * 10 ** 7, 8))),
-        "batch_sample": (("64 of the 4096 config-4 ranges, counted", int((bhi[bsel] - blo[bsel]).sum()),
+        "batch_sample": (("64 of the 4096 seeded batch ranges (seed 0), counted", int((bhi[bsel] - blo[bsel]).sum()),
                           lambda th: batch(bsel, th)),
                          ("16 of those 64", int((bhi[bsel[:16]] - blo[bsel[:16]]).sum()),
                           lambda th: batch(bsel[:16], th))),
-        "serve_sample": (("32 of the config-5 requests of at most 10^8 integers (counted or listed as uint64)",
+        "serve_sample": (("32 of the 2000 seeded serving requests (seed 1) of at most 10^8 integers (counted or listed as uint64)",
                           int((shi[ssel] - slo[ssel]).sum()), lambda th: serve(ssel, th)),
                          ("8 of those 32", int((shi[ssel[:8]] - slo[ssel[:8]]).sum()),
                           lambda th: serve(ssel[:8], th))),

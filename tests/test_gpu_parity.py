@@ -82,7 +82,7 @@ def test_list_random_windows_ragged(sv):
         assert sv.count(lo, hi) == len(want), (lo, hi)
 
 
-def test_config1_full_list(sv, pi_tab):
+def test_full_list_to_1e7(sv, pi_tab):
     lo, hi = 2, 10 ** 7 + 1
     assert sv.count(lo, hi) == pi_tab[10 ** 7]
     got = _u(sv.list(lo, hi, elem_bytes=4), 4)
@@ -91,7 +91,7 @@ def test_config1_full_list(sv, pi_tab):
     assert_same_primes(got, want)
 
 
-def test_config2_full_list(sv, pi_tab):
+def test_full_list_to_1e9(sv, pi_tab):
     lo, hi = 2, 10 ** 9 + 1
     sv.ensure_base_for(hi)
     assert sv.count(lo, hi) == pi_tab[10 ** 9]
