@@ -179,3 +179,14 @@ def test_bench_mark_count_against_brute_force():
                         want += 1
         assert marks == want, (lo, hi)
         assert words == (((hi - base - 1 + 5) // 6) + 31) // 32
+
+
+def test_bench_refuses_several_gpus():
+    # the multi-GPU request is refused before anything touches a device
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
