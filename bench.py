@@ -237,6 +237,17 @@ def bench_batch(pkg, torch, params, workloads, steps=3):
     torch.cuda.synchronize()
     dt_single = time.perf_counter() - t1
     s.close()
+    # kernel time per phase of one batch, by HIP events on the stream the
+    # kernels run on (events need the launches outside a graph)
+    s = pkg.Sieve(0, dict(params, use_graph=0))
+    s.ensure_base_for(int(hi.max()))
+    s.list_batch(lo, hi, mode, out, off, cap, elem_bytes=8)
+    torch.cuda.synchronize()
+    s.set_timing(True)
+    s.list_batch(lo, hi, mode, out, off, cap, elem_bytes=8)
+    torch.cuda.synchronize()
+    sieve_ms, post_ms, bucket_ms, jobs = s.timing_all()
+    s.close()
     ints = int((hi - lo).sum())
     primes = int(counts.sum())
     return {"workload": "4096 ranges (seed 0): lo log-uniform [1e6, 1e15], length log-uniform "
@@ -245,7 +256,9 @@ def bench_batch(pkg, torch, params, workloads, steps=3):
             "ms_per_batch": round(dt * 1e3, 3), "ints_per_s": round(ints / dt, 1),
             "primes_per_s": round(primes / dt, 1),
             "per_range_ms": round(dt_single * 1e3, 3),
-            "batched_vs_per_range": round(dt_single / dt, 3)}
+            "batched_vs_per_range": round(dt_single / dt, 3),
+            "phases_ms": {"sieve": round(sieve_ms, 3), "bucket_fill": round(bucket_ms, 3),
+                          "scan_and_compaction": round(post_ms, 3), "jobs": jobs}}
 
 
 def bench_stream(pkg, torch, params):
