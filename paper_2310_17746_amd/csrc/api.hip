@@ -265,6 +265,7 @@ int install_primes(sieve_ctx *c, uint64_t limit)
                         P.begin());
     c->k_large = std::max(kl, ks);
     c->limit = limit;
+    c->h_pidx = std::move(pidx);
     c->first_mark = fm;
     c->k_split = ks;
     c->k_dense = kd;
@@ -296,6 +297,18 @@ struct Plan {
     uint64_t nvisit = 0, gtiles = 0;  // sieve work units; tiles of split ranges
 };
 
+// Number of base primes <= x, for x <= c->limit: the pi index gives the
+// count up to 64 floor(x / 64) and a short scan adds the primes above it (a
+// binary search over all base primes costs a cache miss per step).
+uint32_t primes_upto(const sieve_ctx *c, uint64_t x)
+{
+    const std::vector<uint32_t> &P = c->h_primes;
+    size_t k = c->h_pidx[x / 64];
+    while (k < P.size() && P[k] <= x)
+        ++k;
+    return (uint32_t)k;
+}
+
 int make_plan(const sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, const uint8_t *mode,
               const uint64_t *off, const uint64_t *cap, int elem_bytes, Plan &pl)
 {
@@ -305,7 +318,8 @@ int make_plan(const sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t
         const uint64_t a = lo[i], b = hi[i];
         if (a > b || b > SIEVE_MAX_HI)
             return SIEVE_E_INVAL;
-        if (b > 4 && isqrt_host(b - 1) > c->limit)
+        const uint64_t root = b > 4 ? isqrt_host(b - 1) : 0;  // largest prime that marks
+        if (root > c->limit)
             return SIEVE_E_RANGE;
         const bool lst = mode && mode[i];
         if (lst && elem_bytes == 4 && b > a && b - 1 > 0xFFFFFFFFull)
@@ -323,10 +337,7 @@ int make_plan(const sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t
         pl.ntiles += nt;
         // Base primes with p * p < hi; on multi-tile ranges the ones from
         // k_large on go through the bucket sieve.
-        d.nact = b > 4 ? (uint32_t)(std::upper_bound(c->h_primes.begin(), c->h_primes.end(),
-                                                     (uint32_t)isqrt_host(b - 1)) -
-                                    c->h_primes.begin())
-                       : 0u;
+        d.nact = b > 4 ? primes_upto(c, root) : 0u;
         // A range takes the bucket sieve when it spans several tiles and its
         // large primes are many: each then costs one start per tile window
         // instead of one per tile, and only its actual hits are walked.
