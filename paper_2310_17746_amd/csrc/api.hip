@@ -529,7 +529,10 @@ enum Phase { kPhaseWhole = 0, kPhaseBucketCount = 1, kPhaseRest = 2, kPhaseDirec
 //   direct:        zero, estimated bucket fill, sieve, finalize, compact
 //   bucket count:  zero, exact bucket count, bucket scan
 //   rest:          exact bucket fill, sieve, finalize, compact
-hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed)
+// With lists false (a job with no list range, launched directly) the segment
+// scans and the compaction, which would find no chunk, are not launched;
+// a captured graph always holds them, since it replays for any job.
+hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed, bool lists)
 {
     const BlobLayout L = blob_layout(c->cap_ranges);
     const JobHeader *job = (const JobHeader *)c->d_blob.p;
@@ -629,7 +632,7 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed)
     g.seg_base = c->d_seg_base.p;
     g.chunk_off = c->d_chunk_off.p;
     g.chunk_vbase = c->d_chunk_vbase.p;
-    if ((e = launch_seg(g, 0, (uint32_t)c->cus * 2, s)) != hipSuccess)
+    if (lists && (e = launch_seg(g, 0, (uint32_t)c->cus * 2, s)) != hipSuccess)
         return e;
     FinalizeArgs f;
     f.job = job;
@@ -640,14 +643,14 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed)
     f.seg_base = c->d_seg_base.p;
     if ((e = launch_finalize(f, kFinalizeGrid, s)) != hipSuccess)
         return e;
-    if ((e = launch_seg(g, 1, (uint32_t)c->cus * 2, s)) != hipSuccess)
+    if (lists && (e = launch_seg(g, 1, (uint32_t)c->cus * 2, s)) != hipSuccess)
         return e;
     CompactArgs k;
     k.job = job;
     k.chunk_vbase = c->d_chunk_vbase.p;
     k.bitmap = c->d_bitmap.p;
     k.chunk_off = c->d_chunk_off.p;
-    if ((e = launch_compact(k, (uint32_t)c->cus * 4, s)) != hipSuccess)
+    if (lists && (e = launch_compact(k, (uint32_t)c->cus * 4, s)) != hipSuccess)
         return e;
     if (timed && (e = hipEventRecord(c->ev[2], s)) != hipSuccess)
         return e;
@@ -667,7 +670,7 @@ hipError_t capture_graph(sieve_ctx *c, int phase)
     hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess)
         return e;
-    hipError_t e2 = enqueue_phase(c, c->stream, phase, false);
+    hipError_t e2 = enqueue_phase(c, c->stream, phase, false, true);
     e = hipStreamEndCapture(c->stream, &c->graph_src[phase]);
     if (e2 != hipSuccess)
         return e2;
@@ -684,7 +687,7 @@ hipError_t capture_graph(sieve_ctx *c, int phase)
 hipError_t run_phase(sieve_ctx *c, hipStream_t s, int phase, bool use_graph)
 {
     if (!use_graph)
-        return enqueue_phase(c, s, phase, c->timing != 0);
+        return enqueue_phase(c, s, phase, c->timing != 0, ((const JobHeader *)c->h_blob)->nlist != 0);
     hipError_t e;
     if (!c->graph[phase] || c->graph_gen[phase] != c->gen) {
         // Capture on the context stream once the work before it is done.
