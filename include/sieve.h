@@ -53,6 +53,7 @@ extern "C" {
 #define SIEVE_E_BUSY (-7)      /* server queue full */
 #define SIEVE_E_CANCELLED (-8) /* request cancelled before it finished */
 #define SIEVE_E_IO (-9)        /* a file could not be created or written */
+#define SIEVE_E_LIMIT (-10)    /* more than the fixed scratch of an allocation-free call holds */
 
 /* Largest accepted hi (ranges are [lo, hi) with hi <= 2^63). */
 #define SIEVE_MAX_HI ((uint64_t)1 << 63)
@@ -206,6 +207,31 @@ int sieve_list_batch(sieve_ctx *ctx, const uint64_t *lo, const uint64_t *hi,
                      const uint8_t *mode, uint64_t n, void *out_dev, const uint64_t *off,
                      const uint64_t *cap, int elem_bytes, uint64_t *counts, int32_t *status,
                      void *stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * batched count as sieve_count_batch, with every piece of job scratch (job
+ * header, range and visit tables, counters, per-range counts and status) in
+ * one fixed device array of SIEVE_STATIC_SCRATCH_BYTES per GPU, held by the
+ * library until the process ends.  The call makes no device or host
+ * allocation: it uses the context's resident base primes (which must already
+ * cover isqrt(hi - 1) of every range, else SIEVE_E_RANGE; they are not
+ * grown), plans into fixed host arrays, copies the plan into the scratch,
+ * launches the sieve kernels on `stream` (NULL: the context stream) and
+ * waits for them; counts[i] (host) then holds the number of primes in
+ * [lo[i], hi[i]).  Every range runs the per-tile marking path: no bucket
+ * sieve and no split tiles (their scratch grows with the job), so the
+ * results equal sieve_count_batch's and long ranges near 2^50 are slower.
+ * Limit: n <= SIEVE_STATIC_MAX_RANGES, else SIEVE_E_LIMIT before any device
+ * work.  All calls on one GPU share its scratch array, so calls that overlap
+ * on the same GPU (from several threads or contexts) race; the library
+ * serialises the calls of one process with a lock.
+ */
+#define SIEVE_STATIC_MAX_RANGES 1024
+#define SIEVE_STATIC_SCRATCH_BYTES 160256
+int sieve_count_batch_static(sieve_ctx *ctx, const uint64_t *lo, const uint64_t *hi, uint64_t n,
+                             uint64_t *counts, void *stream);
 
 /*
  * A rigorous upper bound on the number of primes in [lo, hi), used for

@@ -20,7 +20,8 @@ import os
 import numpy as np
 
 __all__ = ["Sieve", "Server", "Generator", "SieveError", "Params", "list_bound", "wheel_start", "plan_range", "probe_lds",
-           "lib_path", "load_library", "SIEVE_OK", "SIEVE_E_CAPACITY"]
+           "lib_path", "load_library", "SIEVE_OK", "SIEVE_E_CAPACITY", "SIEVE_E_LIMIT",
+           "STATIC_MAX_RANGES"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libsieve.so")
@@ -36,6 +37,8 @@ SIEVE_E_DEVICE = -6
 SIEVE_E_BUSY = -7
 SIEVE_E_CANCELLED = -8
 SIEVE_E_IO = -9
+SIEVE_E_LIMIT = -10
+STATIC_MAX_RANGES = 1024        # ranges per sieve_count_batch_static call
 PRESIEVE_NONE = 0xFFFFFFFF
 BUCKET_NEVER = 0xFFFFFFFF
 BUCKET_EXACT = 1
@@ -120,6 +123,7 @@ def load_library():
         "sieve_list": (ctypes.c_int, [_p, _u64, _u64, _p, _u64, ctypes.c_int,
                                       ctypes.POINTER(_u64), _p]),
         "sieve_count_batch": (ctypes.c_int, [_p, _p, _p, _u64, _p, _p]),
+        "sieve_count_batch_static": (ctypes.c_int, [_p, _p, _p, _u64, _p, _p]),
         "sieve_list_batch": (ctypes.c_int, [_p, _p, _p, _p, _u64, _p, _p, _p, ctypes.c_int,
                                             _p, _p, _p]),
         "sieve_list_bound": (_u64, [_u64, _u64]),
@@ -366,6 +370,19 @@ class Sieve:
         _check(self._lib.sieve_count_batch(self._h, lo.ctypes.data, hi.ctypes.data, lo.size,
                                            counts.ctypes.data, _stream_handle(stream)),
                "sieve_count_batch")
+        return counts
+
+    def count_batch_static(self, lo, hi, stream=None) -> np.ndarray:
+        """As count_batch, through the entry point that allocates nothing
+        (fixed device scratch; at most STATIC_MAX_RANGES ranges per call)."""
+        lo = np.ascontiguousarray(lo, dtype=np.uint64)
+        hi = np.ascontiguousarray(hi, dtype=np.uint64)
+        if lo.shape != hi.shape:
+            raise ValueError("lo and hi differ in shape")
+        counts = np.zeros(lo.shape, dtype=np.uint64)
+        _check(self._lib.sieve_count_batch_static(self._h, lo.ctypes.data, hi.ctypes.data, lo.size,
+                                                  counts.ctypes.data, _stream_handle(stream)),
+               "sieve_count_batch_static")
         return counts
 
     def list_batch(self, lo, hi, mode, out, off, cap, elem_bytes: int = 8, stream=None):

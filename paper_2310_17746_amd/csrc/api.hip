@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -73,6 +74,43 @@ std::vector<uint32_t> host_small_primes(uint64_t limit)
             out.push_back((uint32_t)i);
     return out;
 }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch of sieve_count_batch_static, the entry point for
+// callers that cannot allocate.  It holds one job of at most
+// kStaticMaxRanges count-only ranges: the job header, the range and visit
+// tables, the job counters and the per-range counts and status.  Every GPU
+// the library runs on holds its own copy for the life of the process; host
+// code reaches it only through the address hipGetSymbolAddress returns on
+// that device (kept in the context as static_scratch), never by the
+// array's name.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+struct StaticLayout {
+    static constexpr size_t ranges = align256(sizeof(JobHeader));
+    static constexpr size_t visit = align256(ranges + sizeof(RangeDesc) * kStaticMaxRanges);
+    static constexpr size_t counters = align256(visit + sizeof(VisitEntry) * kStaticMaxRanges);
+    static constexpr size_t counts = align256(counters + sizeof(unsigned long long) * kNumCounters);
+    static constexpr size_t status = align256(counts + sizeof(unsigned long long) * kStaticMaxRanges);
+    static constexpr size_t total = align256(status + sizeof(int32_t) * kStaticMaxRanges);
+};
+
+static_assert(StaticLayout::total == SIEVE_STATIC_SCRATCH_BYTES, "sieve.h states the scratch size");
+
+static __device__ __align__(256) unsigned char scratch[StaticLayout::total];
+
+// Host side of the static path: the plan is built in these arrays (no heap
+// allocation) under g_static_mu, then copied into the device scratch.
+std::mutex g_static_mu;
+JobHeader g_static_job;
+RangeDesc g_static_ranges[kStaticMaxRanges];
+VisitEntry g_static_visit[kStaticMaxRanges];
+uint32_t g_static_order[kStaticMaxRanges];
 
 }  // namespace
 
@@ -1114,6 +1152,8 @@ const char *sieve_strerror(int s)
         return "cancelled";
     case SIEVE_E_IO:
         return "file I/O error";
+    case SIEVE_E_LIMIT:
+        return "request exceeds the fixed scratch of the allocation-free call";
     default:
         return "unknown status";
     }
@@ -1181,6 +1221,17 @@ int sieve_create(sieve_ctx **out, int device, const sieve_params *p)
             destroy_ctx(c);
             return SIEVE_E_DEVICE;
         }
+    {
+        // This device's copy of the fixed scratch array (the device is
+        // current here); host code uses only this address for it.
+        void *sp = nullptr;
+        if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || !sp) {
+            (void)hipGetLastError();
+            destroy_ctx(c);
+            return SIEVE_E_DEVICE;
+        }
+        c->static_scratch = (unsigned char *)sp;
+    }
     st = build_presieve(c, q.presieve_groups == SIEVE_PRESIEVE_NONE ? 0 : q.presieve_groups);
     if (st == SIEVE_OK)
         st = install_primes(c, 0);
@@ -1304,6 +1355,131 @@ int sieve_list_batch(sieve_ctx *ctx, const uint64_t *lo, const uint64_t *hi, con
     int st = run_job(ctx, n, lo, hi, mode, off, cap, elem_bytes, out_dev, counts, status, (hipStream_t)stream,
                      ctx->prm.use_graph != 0);
     return set_err(ctx, st);
+}
+
+int sieve_count_batch_static(sieve_ctx *ctx, const uint64_t *lo, const uint64_t *hi, uint64_t n,
+                             uint64_t *counts, void *stream)
+{
+    if (!ctx || (n && (!lo || !hi || !counts)))
+        return set_err(ctx, SIEVE_E_INVAL);
+    if (n > kStaticMaxRanges)
+        return set_err(ctx, SIEVE_E_LIMIT);
+    if (!ctx->static_scratch)
+        return set_err(ctx, SIEVE_E_DEVICE);
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return set_err(ctx, SIEVE_E_DEVICE);
+    if (n == 0)
+        return set_err(ctx, SIEVE_OK);
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    const uint32_t pw = ctx->prm.segment_bytes / 8;
+    JobHeader &h = g_static_job;
+    memset(&h, 0, sizeof h);
+    uint64_t top = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint64_t a = lo[i], b = hi[i];
+        if (a > b || b > SIEVE_MAX_HI)
+            return set_err(ctx, SIEVE_E_INVAL);
+        const uint64_t root = b > 4 ? isqrt_host(b - 1) : 0;
+        if (root > ctx->limit)
+            return set_err(ctx, SIEVE_E_RANGE);
+        RangeDesc &d = g_static_ranges[i];
+        memset(&d, 0, sizeof d);
+        d.lo = a;
+        d.hi = b;
+        uint64_t nt;
+        plan_range(a, b, pw, nt, d.base, d.last_words);
+        if (nt > 0xFFFFFFFFull)
+            return set_err(ctx, SIEVE_E_INVAL);
+        d.ntiles = (uint32_t)nt;
+        d.tile0 = h.ntiles;
+        h.ntiles += nt;
+        d.nact = b > 4 ? primes_upto(ctx, root) : 0u;
+        d.kbig = d.nact;  // every prime in the per-tile loop: no bucket scratch
+        d.nparts = 1;     // no split tiles: no global plane copies
+        h.nvisit += nt;
+        top = std::max(top, b);
+    }
+    h.nranges = (uint32_t)n;
+    h.elem_bytes = 8;
+    // Visit order: most Table 1 starts per tile first (ties by index).
+    for (uint64_t i = 0; i < n; ++i)
+        g_static_order[i] = (uint32_t)i;
+    std::sort(g_static_order, g_static_order + n, [](uint32_t x, uint32_t y) {
+        const uint32_t kx = g_static_ranges[x].nact, ky = g_static_ranges[y].nact;
+        return kx != ky ? kx > ky : x < y;
+    });
+    uint64_t pos = 0;
+    for (uint64_t j = 0; j < n; ++j) {
+        g_static_visit[j].vstart = pos;
+        g_static_visit[j].range = g_static_order[j];
+        g_static_visit[j].pad = 0;
+        pos += g_static_ranges[g_static_order[j]].ntiles;
+    }
+    unsigned char *const sp = ctx->static_scratch;  // this device's array
+    const JobHeader *job = (const JobHeader *)sp;
+    const RangeDesc *ranges = (const RangeDesc *)(sp + StaticLayout::ranges);
+    unsigned long long *counters = (unsigned long long *)(sp + StaticLayout::counters);
+    unsigned long long *dcounts = (unsigned long long *)(sp + StaticLayout::counts);
+    int32_t *dstatus = (int32_t *)(sp + StaticLayout::status);
+    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    hipError_t e = hipMemcpyAsync(sp, &h, sizeof h, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(sp + StaticLayout::ranges, g_static_ranges, n * sizeof(RangeDesc),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(sp + StaticLayout::visit, g_static_visit, n * sizeof(VisitEntry),
+                           hipMemcpyHostToDevice, s);
+    // counters and counts start at zero (a kernel clears them)
+    if (e == hipSuccess)
+        e = launch_zero(job, counters, dcounts, nullptr, nullptr, nullptr, s);
+    if (e == hipSuccess) {
+        SieveArgs a;
+        memset(&a, 0, sizeof a);
+        a.job = job;
+        a.ranges = ranges;
+        a.visit = (const VisitEntry *)(sp + StaticLayout::visit);
+        a.counters = counters;
+        a.counts = dcounts;
+        a.prm = ctx->d_prm.p;
+        a.pidx = ctx->d_pidx.p;
+        a.pidx_len = (uint32_t)(ctx->limit / 64 + 2);
+        a.nprimes = (uint32_t)ctx->h_primes.size();
+        a.first_mark = ctx->first_mark;
+        a.k_split = ctx->k_split;
+        a.k_dense = ctx->k_dense;
+        a.items = ctx->d_items.p;
+        a.item_prefix = ctx->d_item_prefix.p;
+        a.ps_tab = ctx->d_pstab.p;
+        for (int g = 0; g < kMaxGroups; ++g)
+            a.groups[g] = ctx->groups[g];
+        a.ngroups = ctx->ngroups;
+        a.restore1 = ctx->restore1;
+        a.restore5 = ctx->restore5;
+        a.pw = pw;
+        a.skip5 = ctx->ngroups < 1 || ctx->prm.cofactor_skip == SIEVE_SKIP_NONE ? 0u
+                  : ctx->prm.cofactor_skip == SIEVE_SKIP_ALL ? 1u : 2u;
+        const bool u24 = top < 2 || isqrt_host(top - 1) < (1u << 24) - 8;
+        e = launch_sieve(a, ctx->prm.block_threads, (uint32_t)ctx->cus * ctx->prm.wg_per_cu, u24, s);
+    }
+    if (e == hipSuccess) {
+        FinalizeArgs f;
+        memset(&f, 0, sizeof f);
+        f.job = job;
+        f.ranges = ranges;
+        f.counts = dcounts;
+        f.status = dstatus;
+        e = launch_finalize(f, kFinalizeGrid, s);
+    }
+    unsigned long long flag = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(counts, dcounts, n * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&flag, counters + kErrorFlag, sizeof flag, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return set_err(ctx, hip_status(e));
+    return set_err(ctx, flag ? SIEVE_E_DEVICE : SIEVE_OK);
 }
 
 uint64_t sieve_list_bound(uint64_t lo, uint64_t hi)

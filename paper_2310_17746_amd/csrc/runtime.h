@@ -126,6 +126,10 @@ struct sieve_ctx {
     hipStream_t copy_stream = nullptr;
     hipEvent_t piece_ev[2] = {nullptr, nullptr};
 
+    // Device address of this GPU's fixed scratch array (allocation-free
+    // entry point), looked up once when the context is created.
+    unsigned char *static_scratch = nullptr;
+
     // Optional event timing of the sieve kernel and the post-processing.
     int timing = 0;
     hipEvent_t ev[6]{};

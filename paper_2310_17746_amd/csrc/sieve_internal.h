@@ -35,6 +35,7 @@ constexpr uint32_t kBucketWindow = 2048;    // tiles per bucket work unit (LDS b
 constexpr uint32_t kBucketMinPrimes = 32768; // fewest large primes worth a bucket pass
 constexpr uint32_t kBucketKeep = 4;          // hits per thread the bucket fill replays from LDS
 constexpr uint32_t kPartPrimes = 262144;     // fewest primes (beyond the split items) per part of a split tile
+constexpr uint32_t kStaticMaxRanges = 1024;  // ranges per call of the allocation-free batch count
 
 // One range of a job.  Host-computed plan; read-only on the device.
 struct RangeDesc {
