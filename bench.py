@@ -46,6 +46,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PI_1E11 = 4118054813            # pi(10^11), standard published value
+PI_1E12 = 37607912018           # pi(10^12), standard published value
 LDS_PEAK_GBS = 128 * 256 * 2.4  # nominal LDS bandwidth, GB/s (B/clk/CU * CUs * GHz)
 
 
@@ -328,7 +329,8 @@ def bench_serve(pkg, workloads):
     arrivals = np.cumsum(gaps) / lam * 1e9
     done, st, t0 = run(arrivals)
     lat = np.array([(done[i]["t_done_ns"] - done[i]["t_arrival_ns"]) * 1e-6 for i in range(n)])
-    ok = all(done[i]["status"] == 0 for i in range(n + 1))
+    # every request finished, and the long job's count is pi(10^12)
+    ok = all(done[i]["status"] == 0 for i in range(n + 1)) and int(done[n]["count"]) == PI_1E12
     span = (max(c["t_done_ns"] for c in done.values()) - t0) * 1e-9
     ints = int((hi - lo).sum())
     s.close()

@@ -382,6 +382,7 @@ typedef struct sieve_server_stats {
     uint64_t elapsed_ns;      /* time since creation */
     uint64_t arena_peak_bytes;
     uint64_t queued, active;  /* at the time of the call */
+    uint64_t bucket_steps;    /* steps whose job used the bucket sieve */
 } sieve_server_stats;
 
 /* Creates a server on ctx (p == NULL: defaults).  *srv is set on success. */

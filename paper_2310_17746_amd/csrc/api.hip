@@ -806,6 +806,8 @@ int run_job_once(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *h
     if (e != hipSuccess)
         return hip_status(e);
     const bool buckets = pl.nunits != 0;
+    if (buckets)
+        c->bucket_jobs++;
     {
         // 24-bit start arithmetic when every range's primes are below 2^24 - 8
         uint64_t top = 0;

@@ -74,6 +74,7 @@ struct sieve_ctx {
     std::vector<double> inv_prefix;  // inv_prefix[k] = sum of 1/p over the first k primes
     std::vector<uint32_t> h_pidx;    // h_pidx[s] = number of base primes <= 64 s (s <= limit / 64 + 1)
     uint64_t bucket_fallbacks = 0;   // jobs re-run with the exact bucket layout
+    uint64_t bucket_jobs = 0;        // jobs that ran the bucket sieve
     uint64_t bucket_budget = 0;      // bucket entries one job may hold (larger jobs run in pieces)
     uint32_t bucket_win = 0;         // per-tile LDS bins of the bucket kernels (kernel argument)
     uint32_t sieve_u24 = 0;          // the job's primes are below 2^24 - 8: 24-bit start arithmetic

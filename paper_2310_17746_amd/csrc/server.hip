@@ -265,6 +265,7 @@ void scheduler(sieve_server *s)
         counts.assign(m, 0);
         status.assign(m, 0);
         const uint64_t tb = s->now();
+        const uint64_t bj = c->bucket_jobs;
         if (rc == SIEVE_OK && m)
             rc = sieve::rt::run_job(c, m, lo.data(), hi.data(), mode.data(), off.data(), cap.data(), (int)eb,
                                     s->arena_base, counts.data(), status.data(), nullptr, c->prm.use_graph != 0);
@@ -273,6 +274,8 @@ void scheduler(sieve_server *s)
             std::lock_guard<std::mutex> lk(s->mu);
             s->st.steps++;
             s->st.busy_ns += te - tb;
+            if (c->bucket_jobs != bj)
+                s->st.bucket_steps++;
             for (uint64_t i = 0; i < m; ++i) {
                 Request *r = pieces[i].first;
                 s->st.tiles += pieces[i].second;

@@ -56,3 +56,50 @@ def assert_same_primes(got, want, what=""):
     assert m is None, "%s: lengths %d vs %d, first difference at index %d: got %s, want %s" % (
         what, len(got), len(want), m[0], m[1], m[2])
 
+
+
+# Oracle results of the full-size workloads (tests/golden/make_golden.py):
+# C rows give counts, L rows the SHA-256 digests of each list, per chunk of
+# GOLDEN_CHUNK elements.
+GOLDEN_CHUNK = 1 << 24
+
+
+def read_golden_results(name):
+    """(counts, chunks) from a results file: counts[i] = int and, for listed
+    entries, chunks[i] = [(first, last, n, digest), ...] in chunk order."""
+    counts, chunks = {}, {}
+    for row in read_golden(name):
+        if row[0] == "C":
+            counts[int(row[1])] = int(row[2])
+        elif row[0] == "L":
+            lst = chunks.setdefault(int(row[1]), [])
+            assert int(row[2]) == len(lst), "chunk rows out of order in %s" % name
+            lst.append((int(row[3]), int(row[4]), int(row[5]), row[6]))
+    return counts, chunks
+
+
+def chunk_digests(v):
+    """[(first, last, n, digest)] of a uint64 list, as the golden files hold them."""
+    import hashlib
+
+    import numpy as np
+    v = np.ascontiguousarray(v, dtype="<u8")
+    out = []
+    for s in range(0, len(v), GOLDEN_CHUNK):
+        c = v[s:s + GOLDEN_CHUNK]
+        out.append((int(c[0]), int(c[-1]), len(c), hashlib.sha256(c.tobytes()).hexdigest()[:32]))
+    return out
+
+
+def golden_mismatch(got, want):
+    """None when the digests agree, else a message naming the first differing
+    chunk, its element offset and the value span the oracle gives for it."""
+    if got == want:
+        return None
+    for k in range(max(len(got), len(want))):
+        g = got[k] if k < len(got) else None
+        w = want[k] if k < len(want) else None
+        if g != w:
+            return ("chunk %d (elements from %d): got %s, oracle %s"
+                    % (k, k * GOLDEN_CHUNK, g, w))
+    return "chunk lists differ"
