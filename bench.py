@@ -4,15 +4,22 @@
 One step = one full pass of the sieve over the workload: a sieve_count call
 on [2, 10^11 + 1) (tiling, presieve, Table 1 starts, LDS marking, edge masks,
 popcount, per-range total), with the base primes <= isqrt(10^11) already
-resident in HBM.  Prints one JSON line.
+resident in HBM.  Prints one JSON line.  The launch shape (tile bytes,
+threads, workgroups per CU, tiles per strip) is the autotuner's pick for this
+workload, timed on it first, unless given on the command line.
 
-The roofline entry is for the dominant kernel (k_sieve): its algorithmic LDS
-traffic (4 bytes per mark, read-modify-write of one 32-bit word, plus 8 bytes
-written per plane-word pair at init and 8 bytes read back by the popcount)
-over its average duration, measured with HIP events on the stream it runs
-on, against the nominal LDS bandwidth of the chip (128 B/clk/CU * 256 CUs *
-2.4 GHz).  The mark count is exact: for every base prime p > 61 the number of
-m coprime to 30 with max(p^2, tile base) <= m*p < tile-span end.
+The roofline entry ("bound": "lds") is for the dominant kernel (k_sieve):
+its algorithmic LDS traffic (4 bytes per mark, read-modify-write of one
+32-bit word, plus 8 bytes written per plane-word pair by the presieve and 8
+bytes read back by the popcount) over its average duration, measured with
+HIP events on the stream it runs on, against the nominal LDS bandwidth
+derived from the unit counts (128 B/clk/CU * 256 CUs * 2.4 GHz).  The mark
+count is exact: for every base prime p > 61 the number of m coprime to 30
+with max(p^2, range base) <= m*p < range-span end.  Beside it: the measured
+rate of the instruction itself (LDS probe, this run) and, from the committed
+counter summary of the same kernel sources and launch shape, the LDS bytes
+by counter, the HBM traffic and the VALU lane-ops against the derived VALU
+peak (64 lanes/clk/CU * 256 CUs * 2.4 GHz).
 
 The CPU baseline is the oracle (plain byte-per-integer segmented sieve, all
 host threads) timed on a bounded slice of the same workload.
@@ -48,6 +55,7 @@ sys.path.insert(0, ROOT)
 PI_1E11 = 4118054813            # pi(10^11), standard published value
 PI_1E12 = 37607912018           # pi(10^12), standard published value
 LDS_PEAK_GBS = 128 * 256 * 2.4  # nominal LDS bandwidth, GB/s (B/clk/CU * CUs * GHz)
+VALU_PEAK_LANE_OPS = 64 * 256 * 2.4e9  # int32 VALU lane-ops/s (lanes/clk/CU * CUs * Hz)
 
 
 def small_primes(limit: int) -> np.ndarray:
@@ -112,9 +120,10 @@ def kernel_sources_sha() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per k_sieve dispatch from the committed counter summary, if it
-    was taken on the current kernel sources (else None)."""
+def measured_traffic(params):
+    """Counter figures per k_sieve dispatch from the committed summary, if it
+    was taken on the current kernel sources with the same launch shape (else
+    None)."""
     path = os.path.join(ROOT, "profiles", "k_sieve_pi1e11_traffic.json")
     try:
         with open(path) as f:
@@ -122,6 +131,9 @@ def measured_traffic():
     except (OSError, ValueError):
         return None
     if t.get("kernel_sources_sha256") != kernel_sources_sha():
+        return None
+    shape = ("segment_bytes", "block_threads", "wg_per_cu", "strip_tiles")
+    if any(t.get("params", {}).get(k) != params.get(k) for k in shape):
         return None
     return t
 
@@ -428,6 +440,7 @@ def main() -> int:
     ap.add_argument("--wg-per-cu", type=int, default=0)
     ap.add_argument("--split-hits", type=int, default=0)
     ap.add_argument("--presieve-groups", type=int, default=0)
+    ap.add_argument("--strip-tiles", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline count only")
     ap.add_argument("--cpu-sample", type=int, default=10 ** 11,
@@ -463,7 +476,8 @@ def main() -> int:
     lo, hi = 2, args.hi
     params = {k: v for k, v in dict(segment_bytes=args.segment_bytes, block_threads=args.block_threads,
                                      wg_per_cu=args.wg_per_cu, split_hits=args.split_hits,
-                                     presieve_groups=args.presieve_groups).items() if v}
+                                     presieve_groups=args.presieve_groups,
+                                     strip_tiles=args.strip_tiles).items() if v}
     if args.extra:
         from paper_2310_17746_amd import workloads
         fn = {"list_1e9": lambda: bench_list(pkg, torch, params),
@@ -472,7 +486,16 @@ def main() -> int:
               "serve_2000": lambda: bench_serve(pkg, workloads)}[args.extra]
         print(json.dumps({"extra": args.extra, **fn()}), flush=True)
         return 0
-    s = pkg.Sieve(0, params)
+    # Launch shape of the headline count: the autotuner's pick for this very
+    # workload (timed on it, counts checked against the default's), unless
+    # the shape is given on the command line.
+    hparams, tuned_count = dict(params), None
+    if not any(k in params for k in ("segment_bytes", "block_threads", "wg_per_cu", "strip_tiles")):
+        from paper_2310_17746_amd import autotune
+        print("bench: autotune count", file=sys.stderr, flush=True)
+        tuned_count = autotune.tune("count")
+        hparams.update(tuned_count["params"])
+    s = pkg.Sieve(0, hparams)
     s.ensure_base_for(hi)                     # base primes resident before timing
     prm = s.params.as_dict()
     print("bench: count [%d, %d) params %s" % (lo, hi, prm), file=sys.stderr, flush=True)
@@ -497,12 +520,15 @@ def main() -> int:
     lds_bytes = 4 * marks + 16 * words
     k_ms = sieve_ms / max(jobs, 1)
     achieved = lds_bytes / (k_ms * 1e-3) / 1e9
-    tr = measured_traffic() if hi == 10 ** 11 + 1 else None
-    roof = {"bound": "alu", "resource": "LDS read-modify-write (32-bit words)",
+    tr = measured_traffic(prm) if hi == 10 ** 11 + 1 else None
+    # bound "lds": the marks are 32-bit LDS read-modify-writes, and achieved /
+    # peak is an LDS bandwidth fraction against the nominal LDS rate derived
+    # from the unit counts (128 B/clk/CU x 256 CUs x 2.4 GHz)
+    roof = {"bound": "lds", "resource": "LDS read-modify-write of 32-bit words (ds_or_b32)",
             "achieved": round(achieved, 1), "peak": round(LDS_PEAK_GBS, 1), "unit": "GB/s",
             "frac": round(achieved / LDS_PEAK_GBS, 4),
+            "peak_source": "derived: 128 B/clk/CU x 256 CUs x 2.4 GHz",
             "traffic": (tr["fetch_bytes"] + tr["write_bytes"]) if tr else None,
-            "valu_busy": round(tr["valu_busy"], 4) if tr and "valu_busy" in tr else None,
             "kernel": "k_sieve", "kernel_ms": round(k_ms, 4), "marks": marks,
             "algorithmic_bytes": lds_bytes}
     # Measured peak of the instruction the marks use (32-bit LDS OR), from the
@@ -516,15 +542,19 @@ def main() -> int:
                           "frac_conflict_free": round(achieved / probe["or_linear"], 4),
                           "random_words": round(probe["or_random"], 1),
                           "frac_random_words": round(achieved / probe["or_random"], 4)}
-    if tr and "lds_counter_bytes" in tr:
-        # LDS bytes by the SQ_INSTS_LDS_*_BANDWIDTH counters (64-byte units) of
-        # the committed summary, over this run's kernel time
+    if tr:
+        # from the committed counter summary of the same kernel sources and
+        # launch shape, over this run's kernel time
         cb = tr["lds_counter_bytes"] / (k_ms * 1e-3) / 1e9
         roof["lds_counter"] = {"bytes": int(tr["lds_counter_bytes"]), "GB_per_s": round(cb, 1),
                                "frac_conflict_free": round(cb / probe["or_linear"], 4),
-                               "frac_random_words": round(cb / probe["or_random"], 4),
                                "frac_nominal": round(cb / roof["peak"], 4),
-                               "valu_per_mark": round(tr["valu_per_mark"], 2)}
+                               "bank_conflict_share": round(tr["lds_bank_conflict"], 4)}
+        lane_ops = tr["sq_insts_valu"] * 64 / (k_ms * 1e-3)
+        roof["alu"] = {"achieved": round(lane_ops, 1), "peak": VALU_PEAK_LANE_OPS, "unit": "VALU lane-ops/s",
+                       "frac": round(lane_ops / VALU_PEAK_LANE_OPS, 4),
+                       "peak_source": "derived: 64 lanes/clk/CU (4 SIMD x 16) x 256 CUs x 2.4 GHz",
+                       "valu_per_mark": round(tr["sq_insts_valu"] * 64 / marks, 2)}
 
     s.close()
     extras = None
@@ -581,10 +611,14 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": "u32",
+        "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": "count the primes in [2, 10^11] (half-open [2, 10^11 + 1))",
-                   "lo": lo, "hi": hi, "base_prime_limit": math.isqrt(hi - 1), **prm},
+                   "lo": lo, "hi": hi, "base_prime_limit": math.isqrt(hi - 1), **prm,
+                   "shape_autotune": None if tuned_count is None else {
+                       "chosen": tuned_count["params"], "ms": round(tuned_count["ms"], 3),
+                       "default_ms": round(tuned_count["default_ms"], 3),
+                       "candidates": len(tuned_count["grid"])}},
         "count": int(c),
         "count_ok": count_ok,
         "roofline": roof,

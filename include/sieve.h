@@ -66,9 +66,9 @@ typedef struct sieve_ctx sieve_ctx;
  *   segment_bytes    LDS bytes per tile for the two bit planes together;
  *                    a multiple of 4096 in [8192, 159744] (156 KiB, leaving
  *                    room for the kernel's static LDS in 160 KiB); default
- *                    53248 (52 KiB: three tiles per compute unit).  A tile
+ *                    155648 (152 KiB: one tile per compute unit).  A tile
  *                    covers 24 * segment_bytes consecutive integers.
- *   block_threads    threads per workgroup: 256, 512 or 1024 (default 512).
+ *   block_threads    threads per workgroup: 256, 512 or 1024 (default 1024).
  *   presieve_groups  number of repeating-pattern groups used to initialise
  *                    the planes (0..5; 5 covers every prime 5..61).  0 means
  *                    default; SIEVE_PRESIEVE_NONE disables the presieve.
@@ -110,6 +110,13 @@ typedef struct sieve_ctx sieve_ctx;
  *                    (that order reversed) or SIEVE_VISIT_SHUFFLED (a fixed
  *                    pseudo-random permutation of the ranges).  Results do not
  *                    depend on it; the other two exist for testing.
+ *   strip_tiles      tiles per strip, 1..64 (0, default: about a sixteenth of
+ *                    a resident workgroup's share of the job's tiles, at
+ *                    most 64).  A workgroup sieves the tiles of a strip in
+ *                    order and carries each prime's next hit from one tile
+ *                    to the next (Sec. 2.4), so a prime takes one Table 1
+ *                    start per strip instead of one per tile.  Results do not
+ *                    depend on it.
  */
 typedef struct sieve_params {
     uint32_t segment_bytes;
@@ -124,7 +131,8 @@ typedef struct sieve_params {
     uint32_t bucket_mem_mb;
     uint32_t dense_hits;
     uint32_t visit_order;
-    uint32_t reserved[4];
+    uint32_t strip_tiles;
+    uint32_t reserved[3];
 } sieve_params;
 
 #define SIEVE_PRESIEVE_NONE 0xFFFFFFFFu
@@ -229,7 +237,7 @@ int sieve_list_batch(sieve_ctx *ctx, const uint64_t *lo, const uint64_t *hi,
  * serialises the calls of one process with a lock.
  */
 #define SIEVE_STATIC_MAX_RANGES 1024
-#define SIEVE_STATIC_SCRATCH_BYTES 160256
+#define SIEVE_STATIC_SCRATCH_BYTES 168448
 int sieve_count_batch_static(sieve_ctx *ctx, const uint64_t *lo, const uint64_t *hi, uint64_t n,
                              uint64_t *counts, void *stream);
 

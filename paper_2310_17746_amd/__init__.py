@@ -61,7 +61,7 @@ class Params(ctypes.Structure):
                 ("use_graph", ctypes.c_uint32), ("bucket_slices", ctypes.c_uint32),
                 ("cofactor_skip", ctypes.c_uint32), ("bucket_mem_mb", ctypes.c_uint32),
                 ("dense_hits", ctypes.c_uint32), ("visit_order", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 4)]
+                ("strip_tiles", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

@@ -5,7 +5,7 @@ representative sample of that workload on the GPU at hand, keeps the fastest
 setting, and caches the result in a JSON file keyed by (GPU architecture, CU
 count, workload class).  The knobs are the paper's S (segment bytes per
 tile) and t (threads per workgroup) of Fig. 4, plus workgroups per CU, the
-work-item split, and the bucket-sieve threshold; each candidate is checked
+tiles per strip, and the bucket-sieve threshold; each candidate is checked
 to reproduce the counts of the default setting before it may win.
 
     from paper_2310_17746_amd import autotune
@@ -25,14 +25,16 @@ from . import Sieve, load_library, workloads
 CACHE = os.environ.get("SIEVE_AUTOTUNE_CACHE",
                        os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json"))
 
-# Candidate grids per workload class: (segment_bytes, block_threads, wg_per_cu, split_hits,
-# bucket_threshold).  bucket_threshold 0 = automatic.
-_SEGS = [(32768, 512, 4), (49152, 512, 3), (53248, 512, 3), (77824, 512, 2), (159744, 1024, 1)]
+# Candidate grids per workload class: (segment_bytes, block_threads, wg_per_cu, strip_tiles,
+# bucket_threshold).  0 = automatic.  The default is one 1024-thread workgroup
+# per CU with a 152 KiB tile; the other shapes trade the carried state for
+# more waves per SIMD.
+_SEGS = [(53248, 512, 3), (77824, 512, 2), (155648, 1024, 1), (131072, 1024, 1)]
 GRIDS = {
-    "count": [dict(segment_bytes=sg, block_threads=nt, wg_per_cu=w, split_hits=sp)
-              for sg, nt, w in _SEGS for sp in (32, 64)],
-    "batch": [dict(segment_bytes=sg, block_threads=nt, wg_per_cu=w, split_hits=64, bucket_threshold=bt)
-              for sg, nt, w in _SEGS[1:4] for bt in (0, 8 * sg, 32 * sg)],
+    "count": [dict(segment_bytes=sg, block_threads=nt, wg_per_cu=w, strip_tiles=st)
+              for sg, nt, w in _SEGS for st in (0, 4, 8)],
+    "batch": [dict(segment_bytes=sg, block_threads=nt, wg_per_cu=w, bucket_threshold=bt)
+              for sg, nt, w in _SEGS[:3] for bt in (0, 8 * sg)],
 }
 
 
@@ -46,7 +48,8 @@ def _device_key() -> str:
 def _sample(kind: str):
     """A representative, bounded sample of the workload class."""
     if kind == "count":
-        return np.array([2], dtype=np.uint64), np.array([10 ** 10 + 1], dtype=np.uint64)
+        # the headline count itself (about 10 ms per call)
+        return np.array([2], dtype=np.uint64), np.array([10 ** 11 + 1], dtype=np.uint64)
     if kind == "batch":
         # the whole 4096-range batch (about 10 ms per call): a subset has
         # fewer of the costly high single-tile ranges and ranks settings

@@ -17,7 +17,7 @@
 #include <new>
 #include <vector>
 
-#include "../../include/sieve.h"
+#include "sieve.h"
 #include "runtime.h"
 #include "sieve_internal.h"
 #include "wheel.h"
@@ -28,7 +28,7 @@ hipError_t launch_zero(const JobHeader *job, unsigned long long *counters, unsig
                        uint32_t *bcount, uint32_t *gbm, uint32_t *garrive, hipStream_t s);
 hipError_t launch_bucket(const BucketArgs &a, int pass, uint32_t cus, hipStream_t s);
 hipError_t launch_bucket_scan(const BucketScanArgs &a, hipStream_t s);
-hipError_t launch_sieve(const SieveArgs &a, uint32_t nt, uint32_t grid, bool u24, hipStream_t s);
+hipError_t launch_sieve(const SieveArgs &a, uint32_t nt, uint32_t wg_per_cu, uint32_t grid, bool u24, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs &a, uint32_t grid, hipStream_t s);
 hipError_t launch_seg(const SegArgs &a, int pass, uint32_t grid, hipStream_t s);
 hipError_t launch_compact(const CompactArgs &a, uint32_t grid, hipStream_t s);
@@ -133,13 +133,13 @@ int hip_status(hipError_t e)
 
 void fill_defaults(sieve_params &p)
 {
-    // Defaults from the sweep on MI355X (pi(10^11) count): 52 KiB tiles (three
-    // fill the 160 KiB of LDS), 512 threads and three workgroups per CU
-    // (24 waves), work items of ~64 hits.
+    // Defaults for MI355X: one 1024-thread workgroup per CU with a 152 KiB
+    // tile (nearly all of the 160 KiB of LDS), so that the 128 VGPRs of four
+    // waves per SIMD hold the primes' carried state; work items of ~64 hits.
     if (!p.segment_bytes)
-        p.segment_bytes = 52 * 1024;
+        p.segment_bytes = 152 * 1024;
     if (!p.block_threads)
-        p.block_threads = 512;
+        p.block_threads = 1024;
     if (!p.presieve_groups)
         p.presieve_groups = kMaxGroups;
     if (!p.split_hits)
@@ -168,6 +168,8 @@ int validate_params(const sieve_params &p, uint32_t lds_max)
     if (p.bucket_slices > SIEVE_BUCKET_TINY || p.cofactor_skip > SIEVE_SKIP_SPLIT)
         return SIEVE_E_INVAL;
     if (p.visit_order > SIEVE_VISIT_SHUFFLED)
+        return SIEVE_E_INVAL;
+    if (p.strip_tiles > kMaxStrip)
         return SIEVE_E_INVAL;
     return SIEVE_OK;
 }
@@ -278,11 +280,18 @@ int install_primes(sieve_ctx *c, uint64_t limit)
     }
     if (items.empty())
         items.push_back(make_uint2(0, 0));
-    if (!c->d_prm.reserve(prm.size(), &c->gen) ||
+    // {P, dlt}: the A_five multiples of P lie dlt indices after the A_one
+    // ones (P (P + 4) or P (P + 2) after P * P)
+    std::vector<uint2> prd(std::max<size_t>(n, 1), make_uint2(0, 0));
+    for (size_t k = 0; k < n; ++k)
+        prd[k] = make_uint2(P[k], P[k] % 6 == 1 ? 2 * (P[k] - 1) / 3 : (P[k] - 2) / 3);
+    if (!c->d_prm.reserve(prm.size(), &c->gen) || !c->d_prd.reserve(prd.size(), &c->gen) ||
         !c->d_pidx.reserve(pidx.size(), &c->gen) || !c->d_items.reserve(items.size(), &c->gen) ||
         !c->d_item_prefix.reserve(prefix.size(), &c->gen))
         return SIEVE_E_NOMEM;
     hipError_t e = hipMemcpy(c->d_prm.p, prm.data(), prm.size() * sizeof(PrimeConst), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(c->d_prd.p, prd.data(), prd.size() * sizeof(uint2), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(c->d_pidx.p, pidx.data(), pidx.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess)
@@ -324,6 +333,27 @@ void plan_range(uint64_t lo, uint64_t hi, uint32_t pw, uint64_t &ntiles, uint64_
     const uint64_t words = (n1 + 31) / 32;
     ntiles = (words + pw - 1) / pw;
     last_words = (uint32_t)(words - (ntiles - 1) * pw);
+}
+
+uint32_t strip_tiles(const sieve_ctx *c, uint64_t job_tiles)
+{
+    if (c->prm.strip_tiles)
+        return std::min<uint32_t>(c->prm.strip_tiles, kMaxStrip);
+    const uint64_t wgs = (uint64_t)c->cus * c->prm.wg_per_cu;
+    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kMaxStrip, job_tiles / (16 * wgs)));
+}
+
+void set_strips(RangeDesc &d, uint32_t S)
+{
+    d.strip = d.nparts > 1 ? 1u : std::max<uint32_t>(1, std::min<uint32_t>(S, d.ntiles));
+    d.nstrips = (d.ntiles + d.strip - 1) / d.strip;
+}
+
+// Sieve work units of a range: its strips, or every part of every tile of a
+// split range.
+uint64_t range_units(const RangeDesc &d)
+{
+    return d.nparts > 1 ? (uint64_t)d.ntiles * d.nparts : d.nstrips;
 }
 
 struct Plan {
@@ -442,7 +472,16 @@ int make_plan(const sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t
             d.gtile0 = (uint32_t)pl.gtiles;
             pl.gtiles += d.ntiles;
         }
-        pl.nvisit += (uint64_t)d.ntiles * d.nparts;
+    }
+    // Strips: a workgroup sieves S consecutive tiles of a range and carries
+    // each prime's next hit from tile to tile.  S is about a sixteenth of a
+    // resident workgroup's share of the job's tiles (so the dynamic hand-out
+    // of strips still balances), at most kMaxStrip.
+    const uint32_t S = strip_tiles(c, pl.ntiles);
+    for (uint64_t i = 0; i < n; ++i) {
+        RangeDesc &d = pl.ranges[i];
+        set_strips(d, S);
+        pl.nvisit += range_units(d);
     }
     return SIEVE_OK;
 }
@@ -632,6 +671,7 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed, boo
     a.counters = c->d_counters.p;
     a.counts = c->d_counts.p;
     a.prm = c->d_prm.p;
+    a.prd = c->d_prd.p;
     a.pidx = c->d_pidx.p;
     a.pidx_len = (uint32_t)(c->limit / 64 + 2);
     a.nprimes = (uint32_t)c->h_primes.size();
@@ -657,7 +697,8 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed, boo
     a.bcursor = c->d_bcursor.p;
     if (timed && (e = hipEventRecord(c->ev[0], s)) != hipSuccess)
         return e;
-    e = launch_sieve(a, c->prm.block_threads, (uint32_t)c->cus * c->prm.wg_per_cu, c->sieve_u24 != 0, s);
+    e = launch_sieve(a, c->prm.block_threads, c->prm.wg_per_cu, (uint32_t)c->cus * c->prm.wg_per_cu,
+                     c->sieve_u24 != 0, s);
     if (e != hipSuccess)
         return e;
     if (timed && (e = hipEventRecord(c->ev[1], s)) != hipSuccess)
@@ -795,7 +836,7 @@ int run_job_once(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *h
             v[j].vstart = pos;
             v[j].range = ord[j];
             v[j].pad = 0;
-            pos += (uint64_t)pl.ranges[ord[j]].ntiles * pl.ranges[ord[j]].nparts;
+            pos += range_units(pl.ranges[ord[j]]);
         }
     }
     hipError_t e = hipMemcpyAsync(c->d_blob.p, c->h_blob, L.ranges + n * sizeof(RangeDesc),
@@ -1069,6 +1110,7 @@ void destroy_ctx(sieve_ctx *c)
     if (c->h_btotal)
         (void)hipHostFree(c->h_btotal);
     c->d_prm.release();
+    c->d_prd.release();
     c->d_pidx.release();
     c->d_items.release();
     c->d_item_prefix.release();
@@ -1398,8 +1440,12 @@ int sieve_count_batch_static(sieve_ctx *ctx, const uint64_t *lo, const uint64_t 
         d.nact = b > 4 ? primes_upto(ctx, root) : 0u;
         d.kbig = d.nact;  // every prime in the per-tile loop: no bucket scratch
         d.nparts = 1;     // no split tiles: no global plane copies
-        h.nvisit += nt;
         top = std::max(top, b);
+    }
+    const uint32_t S = strip_tiles(ctx, h.ntiles);
+    for (uint64_t i = 0; i < n; ++i) {
+        set_strips(g_static_ranges[i], S);
+        h.nvisit += range_units(g_static_ranges[i]);
     }
     h.nranges = (uint32_t)n;
     h.elem_bytes = 8;
@@ -1415,7 +1461,7 @@ int sieve_count_batch_static(sieve_ctx *ctx, const uint64_t *lo, const uint64_t 
         g_static_visit[j].vstart = pos;
         g_static_visit[j].range = g_static_order[j];
         g_static_visit[j].pad = 0;
-        pos += g_static_ranges[g_static_order[j]].ntiles;
+        pos += range_units(g_static_ranges[g_static_order[j]]);
     }
     unsigned char *const sp = ctx->static_scratch;  // this device's array
     const JobHeader *job = (const JobHeader *)sp;
@@ -1443,6 +1489,7 @@ int sieve_count_batch_static(sieve_ctx *ctx, const uint64_t *lo, const uint64_t 
         a.counters = counters;
         a.counts = dcounts;
         a.prm = ctx->d_prm.p;
+        a.prd = ctx->d_prd.p;
         a.pidx = ctx->d_pidx.p;
         a.pidx_len = (uint32_t)(ctx->limit / 64 + 2);
         a.nprimes = (uint32_t)ctx->h_primes.size();
@@ -1461,7 +1508,8 @@ int sieve_count_batch_static(sieve_ctx *ctx, const uint64_t *lo, const uint64_t 
         a.skip5 = ctx->ngroups < 1 || ctx->prm.cofactor_skip == SIEVE_SKIP_NONE ? 0u
                   : ctx->prm.cofactor_skip == SIEVE_SKIP_ALL ? 1u : 2u;
         const bool u24 = top < 2 || isqrt_host(top - 1) < (1u << 24) - 8;
-        e = launch_sieve(a, ctx->prm.block_threads, (uint32_t)ctx->cus * ctx->prm.wg_per_cu, u24, s);
+        e = launch_sieve(a, ctx->prm.block_threads, ctx->prm.wg_per_cu, (uint32_t)ctx->cus * ctx->prm.wg_per_cu,
+                         u24, s);
     }
     if (e == hipSuccess) {
         FinalizeArgs f;

@@ -86,31 +86,32 @@ __device__ __forceinline__ void lds_or(uint32_t byte_addr, uint32_t mask)
     __atomic_fetch_or((lds_u32 *)(size_t)byte_addr, mask, __ATOMIC_RELAXED);
 }
 
-// Sets the composite bits start, start + step, ... below nbits of the plane
-// whose words start at LDS byte `base`.  The paper strides by P indices in
-// each array (Sec. 3: adding P to the index adds 6P to the value and keeps
-// the residue mod 6).
-__device__ __forceinline__ void mark_plane(uint32_t base, uint32_t start, uint32_t step, uint32_t nbits)
+// Sets the composite bits start, start + step, ... below end of the plane
+// bit array (A_one bits from 0, A_five bits from 32 pw) and returns the first
+// index at or past end, where the next tile's hits continue.  The paper
+// strides by P indices in each array (Sec. 3: adding P to the index adds 6P
+// to the value and keeps the residue mod 6).
+__device__ __forceinline__ uint32_t mark_run(uint32_t i, uint32_t step, uint32_t end)
 {
-    if (start >= nbits)
-        return;
-    uint32_t i = start;
-    if (step < (nbits >> 2)) {
-        const uint32_t lim = nbits - 3 * step;  // i < lim keeps i + 3*step < nbits
+    if (i >= end)
+        return i;
+    if (step < (end >> 2)) {
+        const uint32_t lim = end - 3 * step;  // i < lim keeps i + 3*step < end
         while (i < lim) {
             // Keep one induction variable in a register (an empty asm operand
             // stops the compiler from splitting it into several).
             asm volatile("" : "+v"(i));
             const uint32_t i1 = i + step, i2 = i1 + step, i3 = i2 + step;
-            lds_or(((i >> 3) & ~3u) + base, 1u << (i & 31));
-            lds_or(((i1 >> 3) & ~3u) + base, 1u << (i1 & 31));
-            lds_or(((i2 >> 3) & ~3u) + base, 1u << (i2 & 31));
-            lds_or(((i3 >> 3) & ~3u) + base, 1u << (i3 & 31));
+            lds_or((i >> 3) & ~3u, 1u << (i & 31));
+            lds_or((i1 >> 3) & ~3u, 1u << (i1 & 31));
+            lds_or((i2 >> 3) & ~3u, 1u << (i2 & 31));
+            lds_or((i3 >> 3) & ~3u, 1u << (i3 & 31));
             i = i3 + step;
         }
     }
-    for (; i < nbits; i += step)
-        lds_or(((i >> 3) & ~3u) + base, 1u << (i & 31));
+    for (; i < end; i += step)
+        lds_or((i >> 3) & ~3u, 1u << (i & 31));
+    return i;
 }
 
 // As mark_plane for a step that is a multiple of 32 bits: every hit then
@@ -185,27 +186,85 @@ __device__ __forceinline__ uint32_t cofactor_mod5(uint32_t b5, uint32_t id, uint
 
 }  // namespace
 
-// Bookkeeping of one tile, kept in LDS after the two planes so that the
-// planes start at LDS address 0 (a mark's address is then (i >> 3) & ~3).
+// Bookkeeping of one strip and its current tile, kept in LDS after the two
+// planes so that the planes start at LDS address 0 (a mark's address is then
+// (i >> 3) & ~3).
 struct TileShared {
-    unsigned long long tile;
     uint32_t range;
+    uint32_t k0, k1;    // the strip: tiles [k0, k1) of the range
+    uint32_t part;      // split tiles: this workgroup's part
+    uint32_t ok;        // a work unit was taken
     uint32_t nact;
     uint32_t sqb, sqe;  // isqrt(tile base), isqrt(tile end - 1), clamped to 32 bits
     uint32_t psoff[kMaxGroups];
     uint32_t red[1024 / 64];
     uint32_t chunk[64];
-    uint32_t part;  // split tiles: this workgroup's part
     uint32_t last;  // split tiles: this workgroup finished the tile's last part
 };
 
-// Three 512-thread workgroups per CU (24 waves, 6 per SIMD) need at most 80
-// VGPRs; the attribute holds the compiler to that.
+// Primes per thread whose next hits stay in registers from one tile of a
+// strip to the next (Sec. 2.4: each prime keeps its place and the sieve goes
+// on from there), for W waves per SIMD: four leave 128 VGPRs per lane, six
+// (three 512-thread workgroups per CU) 80.
+template <int W>
+constexpr int reg_primes()
+{
+    return W <= 4 ? 32 : 8;
+}
+
+// First hit of prime pc in plane A_one, as an index relative to the base B of
+// the first tile of a strip (sqb = isqrt(B), sqe = isqrt(first tile end - 1)).
+// When P*P lies before that tile's end this is the Table 1 start.  Otherwise
+// marking starts at the square itself (Sec. 1.1), and P*P = 1 (mod 6) is the
+// first hit in A_one.  Indices past 2^32 - 1 saturate there; a strip spans
+// far fewer.  (The A_five hits follow from it, at a fixed offset; see below.)
+template <bool U24>
+__device__ __forceinline__ uint32_t strip_start(const PrimeConst &pc, uint32_t sqb, uint32_t sqe, uint64_t B,
+                                                bool narrow)
+{
+    uint32_t id1, id5;
+    if (pc.p <= sqe) {
+        if (U24)
+            tile_start_u24(pc, sqb, B - 1, (uint32_t)B, narrow, id1, id5);
+        else
+            tile_start(pc, sqb, B - 1, (uint32_t)B, narrow, id1, id5);
+        return id1;
+    }
+    const uint64_t P = pc.p;
+    const uint64_t i1 = (P * P - B - 1) / 6;  // P*P lies past the tile, so it is > B; 6 | P*P - 1
+    return i1 > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)i1;
+}
+
+// The multiples of P that fall in A_five are the A_one multiples shifted by
+// dlt indices: P*P is the first hit of A_one, and the next multiple coprime
+// to 6, P (P + 4) for P = 1 (mod 6) or P (P + 2) for P = 5 (mod 6), the
+// first of A_five, dlt = 2 (P - 1) / 3 or (P - 2) / 3 indices later.  So for
+// a tile with base B, given the first A_one hit id1:
+//  - while the square lies at or past B (P > isqrt(B)) the first A_five hit
+//    is id1 + dlt (none in the tile when id1 is past it already);
+//  - once the square lies before B both progressions run through the whole
+//    tile, id1 < P, and the first A_five hit is (id1 + dlt) mod P, which can
+//    lie in the tile when id1 does not.
+
+// W: waves per SIMD the kernel is compiled for (4: one 1024-thread or two
+// 512-thread workgroups per CU; 6: three 512-thread workgroups).
 // U24: every active prime of the job is below 2^24 - 8, so the Table 1
 // starts and the per-item products use the full-rate 24-bit multiplier.
-template <int NT, bool U24>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) k_sieve(SieveArgs a)
+//
+// One work unit is a strip of consecutive tiles of one range (or one part of
+// a split tile).  The workgroup sieves the strip's tiles in order; the first
+// min(n, K * NT) primes after the split items keep their next hit in
+// registers (K per thread) and so need one Table 1 start per strip instead
+// of one per tile; the primes beyond them start afresh in every tile.
+//
+// The planes are all zero whenever a tile begins (the count pass clears
+// every word it reads), so a tile's presieve patterns, marks and bucket
+// entries are all ORed in during one phase, with no barrier between them;
+// one barrier separates marking from counting and one ends the tile.
+template <int NT, int W, bool U24>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W))) k_sieve(SieveArgs a)
 {
+    constexpr int K = reg_primes<W>();
     extern __shared__ uint32_t lds[];
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1);
@@ -214,8 +273,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) k_
     uint32_t *pl1 = lds;  // A_one words
     uint32_t *pl5 = lds + pw;  // A_five words
     const uint32_t base5 = 4 * pw;  // LDS byte address of A_five
+    const uint32_t nbits_full = 32u * pw;  // bits per plane of a whole tile
     TileShared &sh = *reinterpret_cast<TileShared *>(lds + 2 * pw);
-    const uint64_t ntiles = a.job->ntiles;
     const uint64_t nvisit = a.job->nvisit;
     const uint32_t nranges = a.job->nranges;
     if ((uint32_t)(size_t)(__attribute__((address_space(3))) void *)lds != 0) {
@@ -224,15 +283,17 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) k_
             atomicOr(&a.counters[kErrorFlag], 1ull);
         return;
     }
+    for (uint32_t w = tid; w < 2 * pw; w += NT)
+        lds[w] = 0;
 
     for (;;) {
         if (tid == 0) {
             const unsigned long long t = atomicAdd(&a.counters[kTileCounter], 1ull);
-            sh.tile = ntiles;  // none left
+            sh.ok = 0;
             if (t < nvisit) {
                 // t is a visit position: the last visit entry starting at or
                 // before it names the range (entries of empty ranges share
-                // their successor's start, so the last one has tiles).
+                // their successor's start, so the last one has units).
                 uint32_t lo = 0, hi = nranges;
                 while (hi - lo > 1) {
                     const uint32_t mid = (lo + hi) >> 1;
@@ -242,306 +303,389 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) k_
                         hi = mid;
                 }
                 const uint32_t r = a.visit[lo].range;
-                sh.range = r;
                 const RangeDesc &d = a.ranges[r];
-                // unit u of the range: tile u / nparts, part u mod nparts
                 const uint64_t u = t - a.visit[lo].vstart;
-                const uint64_t k = d.nparts > 1 ? u / d.nparts : u;
-                sh.part = (uint32_t)(u - k * d.nparts);
-                sh.tile = d.tile0 + k;  // storage index of the tile
-                const uint32_t nw = (k + 1 == d.ntiles) ? d.last_words : pw;
-                const uint64_t tend = d.base + k * kValsPerWord * pw + kValsPerWord * nw;
-                // Primes p with p * p < tile end (Sec. 4: only primes up to
-                // the square root sieve anything); pidx over-counts by the
-                // few primes in the last 64-wide step, which mark nothing.
-                const uint64_t se = isqrt_dev(tend - 1);
-                uint64_t s = (se + 63) / 64;
-                if (s >= a.pidx_len)
-                    s = a.pidx_len - 1;
-                sh.nact = a.pidx[s];
-                const uint64_t Bt = d.base + k * kValsPerWord * pw;
-                const uint64_t sb = isqrt_dev(Bt);
-                sh.sqe = se > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)se;
-                sh.sqb = sb > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)sb;
+                uint32_t k0, k1, part = 0;
+                if (d.nparts > 1) {
+                    // unit u of a split range: tile u / nparts, part u mod nparts
+                    k0 = (uint32_t)(u / d.nparts);
+                    part = (uint32_t)(u - (uint64_t)k0 * d.nparts);
+                    k1 = k0 + 1;
+                } else {
+                    k0 = (uint32_t)u * d.strip;
+                    k1 = d.ntiles - k0 < d.strip ? d.ntiles : k0 + d.strip;
+                }
+                sh.range = r;
+                sh.k0 = k0;
+                sh.k1 = k1;
+                sh.part = part;
+                sh.ok = 1;
             }
         }
         if (tid < 64)
             sh.chunk[tid] = 0;
         __syncthreads();
-        const unsigned long long t = sh.tile;
-        if (t >= ntiles)
+        if (!sh.ok)
             break;
         const uint32_t rix = sh.range;
         const RangeDesc &d = a.ranges[rix];
-        const uint64_t k = t - d.tile0;
-        const bool first = (k == 0);
-        const bool last = (k + 1 == d.ntiles);
-        const uint32_t nwords = last ? d.last_words : pw;
-        const uint64_t B = d.base + k * kValsPerWord * pw;  // tile value base, multiple of 6
-        const uint64_t tend = B + kValsPerWord * nwords;
-        const uint32_t nbits = nwords * 32;
-
-        const uint32_t part = sh.part;
+        const uint32_t k0 = sh.k0, k1 = sh.k1, part = sh.part;
         const bool split = d.nparts > 1;
-        if (part == 0) {
-            // ---- presieve init: OR of the repeating composite patterns -------
-            if (tid < kMaxGroups)
-                sh.psoff[tid] = (uint32_t)((B / 6) % a.groups[tid].period);
-            __syncthreads();
-            {
-                // Every group is always applied; a disabled group has an all-zero
-                // table, so the loop has no data-dependent branches.
-                uint32_t o[kMaxGroups];
-    #pragma unroll
-                for (int g = 0; g < kMaxGroups; ++g)
-                    o[g] = (sh.psoff[g] + 32u * tid) % a.groups[g].period;
-                for (uint32_t w = tid; w < nwords; w += NT) {
-                    uint2 x[kMaxGroups], y[kMaxGroups];
-    #pragma unroll
-                    for (int g = 0; g < kMaxGroups; ++g) {
-                        const uint2 *tb = a.ps_tab + a.groups[g].offset + (o[g] >> 5);
-                        x[g] = tb[0];
-                        y[g] = tb[1];
-                    }
-                    uint2 c = make_uint2(0, 0);
-    #pragma unroll
-                    for (int g = 0; g < kMaxGroups; ++g) {
-                        const uint32_t sft = o[g] & 31;
-                        c.x |= __builtin_amdgcn_alignbit(y[g].x, x[g].x, sft);
-                        c.y |= __builtin_amdgcn_alignbit(y[g].y, x[g].y, sft);
-                        o[g] += a.groups[g].step;
-                        o[g] = o[g] >= a.groups[g].period ? o[g] - a.groups[g].period : o[g];
-                    }
-                    pl1[w] = c.x;
-                    pl5[w] = c.y;
-                }
-            }
-            __syncthreads();
+        // Primes after the split items that this unit's per-tile loop takes:
+        // up to the bucket sieve's first prime; part 0 of a split tile takes
+        // the first part_primes of them (the later parts take the rest).
+        const uint32_t kcap = d.nact < d.kbig ? d.nact : d.kbig;
+        uint32_t n_rest = kcap > a.k_split ? kcap - a.k_split : 0;
+        if (split && n_rest > d.part_primes)
+            n_rest = d.part_primes;
+        const uint32_t kr0 = a.k_split;
+        const uint32_t kr1 = kr0 + (n_rest < (uint32_t)(K * NT) ? n_rest : (uint32_t)(K * NT));
+        uint32_t id1[K];  // carried next A_one hit of primes kr0 + tid + j NT
 
-            // ---- marking: Table 1 starts, stride P in each plane -------------
-            {
-                // Primes from d.kbig on come from this tile's bucket instead.
-                const uint32_t n_act = sh.nact < d.kbig ? sh.nact : d.kbig;
-                const uint32_t ks = n_act < a.k_split ? n_act : a.k_split;
-                const uint32_t n_items = ks > a.first_mark ? a.item_prefix[ks - a.first_mark] : 0;
-                const uint32_t kd = n_act < a.k_dense ? n_act : a.k_dense;
-                const uint32_t n_dense = kd > a.first_mark ? a.item_prefix[kd - a.first_mark] : 0;
-                uint32_t n_rest = n_act > a.k_split ? n_act - a.k_split : 0;
-                if (split && n_rest > d.part_primes)
-                    n_rest = d.part_primes;  // part 0 of a split tile: its share of the rest
-                const uint32_t n_work = n_items + n_rest;
-                // Every active prime is below 2^31 when the tile ends below 2^62.
+        for (uint32_t k = k0; k < k1; ++k) {
+            const uint64_t t = d.tile0 + k;  // storage index of the tile
+            const bool first = (k == 0);
+            const bool last = (k + 1 == d.ntiles);
+            const uint32_t nwords = last ? d.last_words : pw;
+            const uint64_t B = d.base + (uint64_t)k * kValsPerWord * pw;  // tile value base, multiple of 6
+            const uint64_t tend = B + kValsPerWord * nwords;
+            const uint32_t nbits = nwords * 32;
+            // Primes p with p * p < tile end (Sec. 4: only primes up to the
+            // square root sieve anything); pidx over-counts by the few primes
+            // in the last 64-wide step, which mark nothing.  Every thread
+            // takes these tile values itself (they are uniform).
+            const uint64_t se = isqrt_dev(tend - 1);
+            const uint64_t sb = isqrt_dev(B);
+            const uint32_t sqe = se > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)se;
+            const uint32_t sqb = sb > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)sb;
+            uint64_t ps = (se + 63) / 64;
+            if (ps >= a.pidx_len)
+                ps = a.pidx_len - 1;
+            const uint32_t nact_t = a.pidx[ps];
+
+            if (part == 0) {
+                // ---- presieve: OR of the repeating composite patterns ---------
+                {
+                    // Every group is always applied; a disabled group has an all-zero
+                    // table, so the loop has no data-dependent branches.
+                    const uint64_t b6 = B / 6;
+                    uint32_t o[kMaxGroups];
+#pragma unroll
+                    for (int g = 0; g < kMaxGroups; ++g)
+                        o[g] = (uint32_t)((b6 % a.groups[g].period + 32ull * tid) % a.groups[g].period);
+                    for (uint32_t w = tid; w < nwords; w += NT) {
+                        uint2 x[kMaxGroups], y[kMaxGroups];
+#pragma unroll
+                        for (int g = 0; g < kMaxGroups; ++g) {
+                            const uint2 *tb = a.ps_tab + a.groups[g].offset + (o[g] >> 5);
+                            x[g] = tb[0];
+                            y[g] = tb[1];
+                        }
+                        uint2 c = make_uint2(0, 0);
+#pragma unroll
+                        for (int g = 0; g < kMaxGroups; ++g) {
+                            const uint32_t sft = o[g] & 31;
+                            c.x |= __builtin_amdgcn_alignbit(y[g].x, x[g].x, sft);
+                            c.y |= __builtin_amdgcn_alignbit(y[g].y, x[g].y, sft);
+                            o[g] += a.groups[g].step;
+                            o[g] = o[g] >= a.groups[g].period ? o[g] - a.groups[g].period : o[g];
+                        }
+                        lds_or(4u * w, c.x);
+                        lds_or(base5 + 4u * w, c.y);
+                    }
+                }
+
+                // ---- marking: Table 1 starts, stride P in each plane -------------
+                {
+                    // Primes from d.kbig on come from this tile's bucket instead.
+                    const uint32_t n_act = nact_t < d.kbig ? nact_t : d.kbig;
+                    const uint32_t ks = n_act < a.k_split ? n_act : a.k_split;
+                    const uint32_t n_items = ks > a.first_mark ? a.item_prefix[ks - a.first_mark] : 0;
+                    const uint32_t kd = n_act < a.k_dense ? n_act : a.k_dense;
+                    const uint32_t n_dense = kd > a.first_mark ? a.item_prefix[kd - a.first_mark] : 0;
+                    // primes past the registers' share start afresh in this tile
+                    const uint32_t kf1 = n_act < kr0 + n_rest ? n_act : kr0 + n_rest;
+                    const uint32_t n_fresh = kf1 > kr1 ? kf1 - kr1 : 0;
+                    const uint32_t n_work = n_items + n_fresh;
+                    // Every active prime is below 2^31 when the tile ends below 2^62.
+                    const bool narrow = tend <= (1ull << 62);
+                    const uint32_t b5 = (uint32_t)(B % 5);
+                    const uint64_t Bm1 = B - 1;
+                    const uint32_t B32 = (uint32_t)B;
+                    // Plane A_five is addressed as bits [32 pw, 32 pw + nbits) of one
+                    // array that starts with A_one, so a mark needs no base add.
+                    const uint32_t off5 = 32u * pw;
+                    // Two work units per thread per pass, their loads issued
+                    // together (an item, then its prime's constants).
+                    constexpr uint32_t kQ = 2;
+                    for (uint32_t vb = tid; vb < n_work; vb += kQ * NT) {
+                        uint32_t kps[kQ], js[kQ], gs[kQ];
+#pragma unroll
+                        for (uint32_t q = 0; q < kQ; ++q) {
+                            const uint32_t v = vb + q * NT;
+                            if (v < n_items) {
+                                const uint2 it = a.items[v];
+                                kps[q] = it.x;
+                                js[q] = it.y >> 16;
+                                gs[q] = it.y & 0xFFFFu;
+                            } else {
+                                kps[q] = kr1 + (v - n_items);
+                                js[q] = 0;
+                                gs[q] = 1;
+                            }
+                        }
+                        PrimeConst pcs[kQ];
+#pragma unroll
+                        for (uint32_t q = 0; q < kQ; ++q)
+                            if (vb + q * NT < n_work)
+                                pcs[q] = a.prm[kps[q]];
+#pragma unroll
+                        for (uint32_t q = 0; q < kQ; ++q) {
+                            const uint32_t v = vb + q * NT;
+                            const PrimeConst &pc = pcs[q];
+                            if (v >= n_work || pc.p > sqe)
+                                continue;  // past the work, or P * P >= tile end: nothing to mark
+                            const uint32_t j = js[q], g = gs[q];
+                            uint32_t id1t, id5t;
+                            uint32_t step, off;
+                            if (U24) {
+                                tile_start_u24(pc, sqb, Bm1, B32, narrow, id1t, id5t);
+                                step = __umul24(g, pc.p & 0xFFFFFFu);  // g, j < 2^16
+                                off = __umul24(j, pc.p & 0xFFFFFFu);
+                            } else {
+                                tile_start(pc, sqb, Bm1, B32, narrow, id1t, id5t);
+                                step = g * pc.p;
+                                off = j * pc.p;
+                            }
+                            if (v < n_dense) {
+                                // g is a multiple of 32: fixed-mask marking
+                                mark_plane_fixed(id1t + off, step, nbits);
+                                mark_plane_fixed(id5t + off + off5, step, nbits + off5);
+                            } else if (a.skip5 == 1 || (a.skip5 == 2 && v < n_items)) {
+                                // hit n of this lane has cofactor m0 + 6(j + n g) = c + n g (mod 5);
+                                // it is a multiple of 5 when n = -c / g (mod 5)
+                                const uint32_t inv5 = pc.r >> 29;
+                                const uint32_t ginv = inv_mod5(g);
+                                const uint32_t c1 = (cofactor_mod5(b5, id1t, 1, inv5) + j) % 5u;
+                                const uint32_t c5 = (cofactor_mod5(b5, id5t, 0, inv5) + j) % 5u;
+                                mark_plane_skip5(0, id1t + off, step, nbits, ((5u - c1) * ginv) % 5u);
+                                mark_plane_skip5(0, id5t + off + off5, step, nbits + off5, ((5u - c5) * ginv) % 5u);
+                            } else {
+                                (void)mark_run(id1t + off, step, nbits);
+                                (void)mark_run(id5t + off + off5, step, nbits + off5);
+                            }
+                        }
+                    }
+                    // Register-carried primes kr0 + tid + j NT: their starts are
+                    // taken once, in the strip's first tile; afterwards each
+                    // continues from its last hit, shifted by one tile.
+                    {
+                        const bool init = k == k0;
+                        // The slot index is opaque per tile, so that the compiler
+                        // does not hoist the K slots' addresses out of the tile
+                        // loop (they would stay live in 4 K registers).
+                        uint32_t kb = kr0 + tid;
+                        asm volatile("" : "+v"(kb));
+                        uint2 pn = kb < kr1 ? a.prd[kb] : make_uint2(0, 0);
+#pragma unroll
+                        for (int jj = 0; jj < K; ++jj) {
+                            const uint32_t kp = kb + (uint32_t)jj * NT;
+                            const uint32_t p = pn.x, dlt = pn.y;
+                            const uint32_t kn = kp + NT;
+                            if (jj + 1 < K)
+                                pn = kn < kr1 ? a.prd[kn] : make_uint2(0, 0);
+                            uint32_t x1 = id1[jj];
+                            if (init) {
+                                x1 = 0xFFFFFFFFu;
+                                if (kp < kr1)
+                                    x1 = strip_start<U24>(a.prm[kp], sqb, sqe, B, narrow);
+                            }
+                            // (p = 0 past kr1: the index there stays saturated, no mark)
+                            if (p <= sqb) {
+                                // square before the tile: x1 < P; (x1 + dlt) mod P
+                                // without overflowing 32 bits
+                                const uint32_t x5 = x1 >= p - dlt ? x1 - (p - dlt) : x1 + dlt;
+                                if (x5 < nbits)
+                                    (void)mark_run(x5 + off5, p, nbits + off5);
+                                if (x1 < nbits)
+                                    x1 = mark_run(x1, p, nbits);
+                            } else if (x1 < nbits) {
+                                // the square lies in this tile: both progressions start there
+                                (void)mark_run(x1 + dlt + off5, p, nbits + off5);
+                                x1 = mark_run(x1, p, nbits);
+                            }
+                            id1[jj] = x1 - nbits_full;
+                        }
+                    }
+                    // Bucket entries of this tile: one mark each (entries past
+                    // the last tile's words mark nothing of the range).
+                    if (d.kbig < d.nact) {
+                        const bool est = a.job->bmode == 1;
+                        const uint64_t e0 = est ? d.bbase + (uint64_t)k * d.bcap : a.boff[t];
+                        uint64_t ne = est ? a.bcursor[t] : a.bcount[t];
+                        if (est && ne > d.bcap)
+                            ne = d.bcap;  // overflowed slice: the job is run again exactly
+                        for (uint64_t e = tid; e < ne; e += NT) {
+                            const uint32_t v = a.bdata[e0 + e];
+                            const uint32_t bit = v & 0x7FFFFFFFu;
+                            if (bit < nbits)
+                                lds_or(((bit >> 3) & ~3u) + ((v >> 31) ? base5 : 0u), 1u << (bit & 31));
+                        }
+                    }
+                }
+                __syncthreads();
+
+            } else {
+                // ---- a later part of a split tile: primes k_split + [part C,
+                // (part + 1) C) with C = d.part_primes, marked straight into the
+                // tile's global planes (they are large: few hits each).  This
+                // workgroup's own planes stay zero.
+                const uint32_t n_act = nact_t < d.kbig ? nact_t : d.kbig;
+                const uint32_t n_rest_t = n_act > a.k_split ? n_act - a.k_split : 0;
+                const uint32_t C = d.part_primes;
+                const uint32_t r0 = part * C;
+                const uint32_t r1 = n_rest_t < r0 + C ? n_rest_t : r0 + C;
                 const bool narrow = tend <= (1ull << 62);
-                const uint32_t b5 = (uint32_t)(B % 5);
-                const uint32_t sqb = sh.sqb, sqe = sh.sqe;
                 const uint64_t Bm1 = B - 1;
                 const uint32_t B32 = (uint32_t)B;
-                // Plane A_five is addressed as bits [32 pw, 32 pw + nbits) of one
-                // array that starts with A_one, so a mark needs no base add.
-                const uint32_t off5 = 32u * pw;
-                for (uint32_t v = tid; v < n_work; v += NT) {
-                    uint32_t kp, j, g;
-                    if (v < n_items) {
-                        const uint2 it = a.items[v];
-                        kp = it.x;
-                        j = it.y >> 16;
-                        g = it.y & 0xFFFFu;
-                    } else {
-                        kp = a.k_split + (v - n_items);
-                        j = 0;
-                        g = 1;
-                    }
-                    const PrimeConst pc = a.prm[kp];
-                    if (pc.p > sqe)
-                        continue;  // P * P >= tile end: nothing to mark
-                    uint32_t id1, id5;
-                    uint32_t step, off;
-                    if (U24) {
-                        tile_start_u24(pc, sqb, Bm1, B32, narrow, id1, id5);
-                        step = __umul24(g, pc.p & 0xFFFFFFu);  // g, j < 2^16
-                        off = __umul24(j, pc.p & 0xFFFFFFu);
-                    } else {
-                        tile_start(pc, sqb, Bm1, B32, narrow, id1, id5);
-                        step = g * pc.p;
-                        off = j * pc.p;
-                    }
-                    if (v < n_dense) {
-                        // g is a multiple of 32: fixed-mask marking
-                        mark_plane_fixed(id1 + off, step, nbits);
-                        mark_plane_fixed(id5 + off + off5, step, nbits + off5);
-                    } else if (a.skip5 == 1 || (a.skip5 == 2 && v < n_items)) {
-                        // hit n of this lane has cofactor m0 + 6(j + n g) = c + n g (mod 5);
-                        // it is a multiple of 5 when n = -c / g (mod 5)
-                        const uint32_t inv5 = pc.r >> 29;
-                        const uint32_t ginv = inv_mod5(g);
-                        const uint32_t c1 = (cofactor_mod5(b5, id1, 1, inv5) + j) % 5u;
-                        const uint32_t c5 = (cofactor_mod5(b5, id5, 0, inv5) + j) % 5u;
-                        mark_plane_skip5(0, id1 + off, step, nbits, ((5u - c1) * ginv) % 5u);
-                        mark_plane_skip5(0, id5 + off + off5, step, nbits + off5, ((5u - c5) * ginv) % 5u);
-                    } else {
-                        mark_plane(0, id1 + off, step, nbits);
-                        mark_plane(0, id5 + off + off5, step, nbits + off5);
-                    }
-                }
-                // Bucket entries of this tile: one mark each.
-                if (d.kbig < d.nact) {
-                    const bool est = a.job->bmode == 1;
-                    const uint64_t e0 = est ? d.bbase + k * d.bcap : a.boff[t];
-                    uint64_t ne = est ? a.bcursor[t] : a.bcount[t];
-                    if (est && ne > d.bcap)
-                        ne = d.bcap;  // overflowed slice: the job is run again exactly
-                    for (uint64_t e = tid; e < ne; e += NT) {
-                        const uint32_t v = a.bdata[e0 + e];
-                        const uint32_t bit = v & 0x7FFFFFFFu;
-                        lds_or(((bit >> 3) & ~3u) + ((v >> 31) ? base5 : 0u), 1u << (bit & 31));
+                uint32_t *const g1 = a.gbm + ((uint64_t)d.gtile0 + k) * 2 * pw;
+                uint32_t *const g5 = g1 + pw;
+                // Four primes per thread per pass, their constants loaded
+                // together: the table of a high tile lies beyond L2, so the
+                // loads' latency, not the arithmetic, bounds this loop.
+                constexpr uint32_t kQ = 4;
+                for (uint32_t rb = r0 + tid; rb < r1; rb += kQ * NT) {
+                    PrimeConst pcs[kQ];
+#pragma unroll
+                    for (uint32_t q = 0; q < kQ; ++q)
+                        if (rb + q * NT < r1)
+                            pcs[q] = a.prm[a.k_split + rb + q * NT];
+#pragma unroll
+                    for (uint32_t q = 0; q < kQ; ++q) {
+                        const PrimeConst &pc = pcs[q];
+                        if (rb + q * NT >= r1 || pc.p > sqe)
+                            continue;  // past the part, or P * P >= tile end
+                        uint32_t id1t, id5t;
+                        if (U24)
+                            tile_start_u24(pc, sqb, Bm1, B32, narrow, id1t, id5t);
+                        else
+                            tile_start(pc, sqb, Bm1, B32, narrow, id1t, id5t);
+                        // i < nbits < 2^20 and P < 2^32 - 2^20: i + P does not wrap
+                        for (uint32_t i = id1t; i < nbits; i += pc.p)
+                            atomicOr(&g1[i >> 5], 1u << (i & 31));
+                        for (uint32_t i = id5t; i < nbits; i += pc.p)
+                            atomicOr(&g5[i >> 5], 1u << (i & 31));
                     }
                 }
             }
-            __syncthreads();
 
-        } else {
-            // ---- a later part of a split tile: primes k_split + [part C,
-            // (part + 1) C) with C = d.part_primes, marked straight into the
-            // tile's global planes (they are large: few hits each)
-            const uint32_t n_act = sh.nact < d.kbig ? sh.nact : d.kbig;
-            const uint32_t n_rest = n_act > a.k_split ? n_act - a.k_split : 0;
-            const uint32_t C = d.part_primes;
-            const uint32_t r0 = part * C;
-            const uint32_t r1 = n_rest < r0 + C ? n_rest : r0 + C;
-            const bool narrow = tend <= (1ull << 62);
-            const uint32_t sqb = sh.sqb, sqe = sh.sqe;
-            const uint64_t Bm1 = B - 1;
-            const uint32_t B32 = (uint32_t)B;
-            uint32_t *const g1 = a.gbm + ((uint64_t)d.gtile0 + k) * 2 * pw;
-            uint32_t *const g5 = g1 + pw;
-            // Four primes per thread per pass, their constants loaded
-            // together: the table of a high tile lies beyond L2, so the
-            // loads' latency, not the arithmetic, bounds this loop.
-            constexpr uint32_t kQ = 4;
-            for (uint32_t rb = r0 + tid; rb < r1; rb += kQ * NT) {
-                PrimeConst pcs[kQ];
-#pragma unroll
-                for (uint32_t q = 0; q < kQ; ++q)
-                    if (rb + q * NT < r1)
-                        pcs[q] = a.prm[a.k_split + rb + q * NT];
-#pragma unroll
-                for (uint32_t q = 0; q < kQ; ++q) {
-                    const PrimeConst &pc = pcs[q];
-                    if (rb + q * NT >= r1 || pc.p > sqe)
-                        continue;  // past the part, or P * P >= tile end
-                    uint32_t id1, id5;
-                    if (U24)
-                        tile_start_u24(pc, sqb, Bm1, B32, narrow, id1, id5);
-                    else
-                        tile_start(pc, sqb, Bm1, B32, narrow, id1, id5);
-                    // i < nbits < 2^20 and P < 2^32 - 2^20: i + P does not wrap
-                    for (uint32_t i = id1; i < nbits; i += pc.p)
-                        atomicOr(&g1[i >> 5], 1u << (i & 31));
-                    for (uint32_t i = id5; i < nbits; i += pc.p)
-                        atomicOr(&g5[i >> 5], 1u << (i & 31));
-                }
-            }
-        }
-
-        // ---- split tiles: the parts meet in the global planes; the
-        // workgroup that finishes the last part counts or lists the tile
-        if (split) {
-            uint32_t *const g1 = a.gbm + ((uint64_t)d.gtile0 + k) * 2 * pw;
-            if (part == 0)
-                for (uint32_t w = tid; w < nwords; w += NT) {
-                    if (pl1[w])
-                        atomicOr(&g1[w], pl1[w]);
-                    if (pl5[w])
-                        atomicOr(&g1[pw + w], pl5[w]);
-                }
-            __threadfence();  // this workgroup's marks are done before it arrives
-            __syncthreads();
-            if (tid == 0)
-                sh.last = atomicAdd(&a.garrive[(uint64_t)d.gtile0 + k], 1u) + 1u == d.nparts ? 1u : 0u;
-            __syncthreads();
-            if (sh.last == 0) {
+            // ---- split tiles: the parts meet in the global planes; the
+            // workgroup that finishes the last part counts or lists the tile
+            if (split) {
+                uint32_t *const g1 = a.gbm + ((uint64_t)d.gtile0 + k) * 2 * pw;
+                if (part == 0)
+                    for (uint32_t w = tid; w < nwords; w += NT) {
+                        const uint32_t c1 = pl1[w], c5 = pl5[w];
+                        if (c1)
+                            atomicOr(&g1[w], c1);
+                        if (c5)
+                            atomicOr(&g1[pw + w], c5);
+                        pl1[w] = 0;
+                        pl5[w] = 0;
+                    }
+                __threadfence();  // this workgroup's marks are done before it arrives
                 __syncthreads();
-                continue;  // another part's workgroup finishes the tile
+                if (tid == 0)
+                    sh.last = atomicAdd(&a.garrive[(uint64_t)d.gtile0 + k], 1u) + 1u == d.nparts ? 1u : 0u;
+                __syncthreads();
+                if (sh.last == 0) {
+                    __syncthreads();
+                    continue;  // another part's workgroup finishes the tile
+                }
+                __threadfence();
+                for (uint32_t w = tid; w < nwords; w += NT) {
+                    pl1[w] = __hip_atomic_load(&g1[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    pl5[w] = __hip_atomic_load(&g1[pw + w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                __syncthreads();
             }
-            __threadfence();
-            for (uint32_t w = tid; w < nwords; w += NT) {
-                pl1[w] = __hip_atomic_load(&g1[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                pl5[w] = __hip_atomic_load(&g1[pw + w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            __syncthreads();
-        }
 
-        // ---- edges, then count or bitmap ---------------------------------
-        uint32_t head1 = 0, head5 = 0, tail1 = 0, tail5 = 0;
-        if (first) {
-            if (B + 1 < d.lo || B == 0)
-                head1 = 1;  // below lo, or the value 1
-            if (B + 5 < d.lo)
-                head5 = 1;
-        }
-        if (last) {
-            const uint64_t base_i = 32ull * (nwords - 1);
-            const uint64_t n1 = d.hi > B + 1 ? (d.hi - B - 1 + 5) / 6 : 0;
-            const uint64_t n5 = d.hi > B + 5 ? (d.hi - B - 5 + 5) / 6 : 0;
-            const uint64_t r1 = n1 > base_i ? n1 - base_i : 0;
-            const uint64_t r5 = n5 > base_i ? n5 - base_i : 0;
-            tail1 = r1 >= 32 ? 0u : (~0u << r1);
-            tail5 = r5 >= 32 ? 0u : (~0u << r5);
-        }
-        const bool list = d.mode != 0;
-        const uint32_t nw_pad = list ? ((nwords + kChunkWords - 1) / kChunkWords) * kChunkWords : nwords;
-        const uint64_t wbase = list ? (d.chunk0 + k * (pw / kChunkWords)) * kChunkWords : 0;
-        uint32_t cnt = 0;
-        for (uint32_t w = tid; w < nw_pad; w += NT) {
-            uint32_t p1 = 0, p5 = 0;
-            if (w < nwords) {
-                uint32_t c1 = pl1[w], c5 = pl5[w];
-                if (w == 0 && B < 62) {
-                    // The presieved primes themselves (5..61) lie in word 0
-                    // of any tile based below 62: the patterns marked them.
-                    c1 &= ~(a.restore1 >> (B / 6));
-                    c5 &= ~(a.restore5 >> (B / 6));
-                }
-                if (w == 0) {
-                    c1 |= head1;
-                    c5 |= head5;
-                }
-                if (w == nwords - 1) {
-                    c1 |= tail1;
-                    c5 |= tail5;
-                }
-                p1 = ~c1;
-                p5 = ~c5;
+            // ---- edges, then count or bitmap; every word read is cleared ------
+            uint32_t head1 = 0, head5 = 0, tail1 = 0, tail5 = 0;
+            if (first) {
+                if (B + 1 < d.lo || B == 0)
+                    head1 = 1;  // below lo, or the value 1
+                if (B + 5 < d.lo)
+                    head5 = 1;
             }
-            const uint32_t c = __popc(p1) + __popc(p5);
+            if (last) {
+                const uint64_t base_i = 32ull * (nwords - 1);
+                const uint64_t n1 = d.hi > B + 1 ? (d.hi - B - 1 + 5) / 6 : 0;
+                const uint64_t n5 = d.hi > B + 5 ? (d.hi - B - 5 + 5) / 6 : 0;
+                const uint64_t r1 = n1 > base_i ? n1 - base_i : 0;
+                const uint64_t r5 = n5 > base_i ? n5 - base_i : 0;
+                tail1 = r1 >= 32 ? 0u : (~0u << r1);
+                tail5 = r5 >= 32 ? 0u : (~0u << r5);
+            }
+            const bool list = d.mode != 0;
+            const uint32_t nw_pad = list ? ((nwords + kChunkWords - 1) / kChunkWords) * kChunkWords : nwords;
+            const uint64_t wbase = list ? (d.chunk0 + k * (pw / kChunkWords)) * kChunkWords : 0;
+            uint32_t cnt = 0;
+            for (uint32_t w = tid; w < nw_pad; w += NT) {
+                uint32_t p1 = 0, p5 = 0;
+                if (w < nwords) {
+                    uint32_t c1 = pl1[w], c5 = pl5[w];
+                    pl1[w] = 0;
+                    pl5[w] = 0;
+                    if (w == 0 && B < 62) {
+                        // The presieved primes themselves (5..61) lie in word 0
+                        // of any tile based below 62: the patterns marked them.
+                        c1 &= ~(a.restore1 >> (B / 6));
+                        c5 &= ~(a.restore5 >> (B / 6));
+                    }
+                    if (w == 0) {
+                        c1 |= head1;
+                        c5 |= head5;
+                    }
+                    if (w == nwords - 1) {
+                        c1 |= tail1;
+                        c5 |= tail5;
+                    }
+                    p1 = ~c1;
+                    p5 = ~c5;
+                }
+                const uint32_t c = __popc(p1) + __popc(p5);
+                if (list) {
+                    a.bitmap[wbase + w] = spread32(p1) | (spread32(p5) << 1);
+                    const uint32_t ws = wave_sum(c);
+                    if (lane == 0)
+                        atomicAdd(&sh.chunk[w / kChunkWords], ws);
+                } else {
+                    cnt += c;
+                }
+            }
             if (list) {
-                a.bitmap[wbase + w] = spread32(p1) | (spread32(p5) << 1);
-                const uint32_t ws = wave_sum(c);
-                if (lane == 0)
-                    atomicAdd(&sh.chunk[w / kChunkWords], ws);
+                __syncthreads();
+                const uint32_t nch = nw_pad / kChunkWords;
+                const uint64_t cbase = d.chunk0 + k * (pw / kChunkWords);
+                if (tid < nch) {
+                    a.chunk_counts[cbase + tid] = sh.chunk[tid];
+                    sh.chunk[tid] = 0;  // for the strip's next tile
+                }
             } else {
-                cnt += c;
+                cnt = wave_sum(cnt);
+                if (lane == 0)
+                    sh.red[wave] = cnt;
+                __syncthreads();
+                if (tid == 0) {
+                    uint32_t tot = 0;
+                    for (uint32_t i = 0; i < NT / kWave; ++i)
+                        tot += sh.red[i];
+                    atomicAdd(&a.counts[rix], (unsigned long long)tot);
+                }
             }
-        }
-        if (list) {
             __syncthreads();
-            const uint32_t nch = nw_pad / kChunkWords;
-            const uint64_t cbase = d.chunk0 + k * (pw / kChunkWords);
-            if (tid < nch)
-                a.chunk_counts[cbase + tid] = sh.chunk[tid];
-        } else {
-            cnt = wave_sum(cnt);
-            if (lane == 0)
-                sh.red[wave] = cnt;
-            __syncthreads();
-            if (tid == 0) {
-                uint32_t tot = 0;
-                for (uint32_t i = 0; i < NT / kWave; ++i)
-                    tot += sh.red[i];
-                atomicAdd(&a.counts[rix], (unsigned long long)tot);
-            }
         }
-        __syncthreads();
     }
 }
 
@@ -1177,9 +1321,11 @@ __global__ void k_zero(const JobHeader *job, unsigned long long *counters, unsig
 hipError_t set_sieve_lds_limit(uint32_t segment_bytes)
 {
     const int bytes = (int)(segment_bytes + sizeof(TileShared));
-    const void *fns[] = {(const void *)k_sieve<256, false>, (const void *)k_sieve<512, false>,
-                         (const void *)k_sieve<1024, false>, (const void *)k_sieve<256, true>,
-                         (const void *)k_sieve<512, true>, (const void *)k_sieve<1024, true>};
+    const void *fns[] = {(const void *)k_sieve<256, 4, false>,  (const void *)k_sieve<256, 6, false>,
+                         (const void *)k_sieve<512, 4, false>,  (const void *)k_sieve<512, 6, false>,
+                         (const void *)k_sieve<1024, 4, false>, (const void *)k_sieve<256, 4, true>,
+                         (const void *)k_sieve<256, 6, true>,   (const void *)k_sieve<512, 4, true>,
+                         (const void *)k_sieve<512, 6, true>,   (const void *)k_sieve<1024, 4, true>};
     for (const void *f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess)
@@ -1249,17 +1395,23 @@ hipError_t launch_bucket_scan(const BucketScanArgs &a, hipStream_t s)
 namespace {
 
 template <bool U24>
-hipError_t launch_sieve_t(const SieveArgs &a, uint32_t nt, uint32_t grid, size_t lds, hipStream_t s)
+hipError_t launch_sieve_t(const SieveArgs &a, uint32_t nt, bool six, uint32_t grid, size_t lds, hipStream_t s)
 {
     switch (nt) {
     case 256:
-        hipLaunchKernelGGL((k_sieve<256, U24>), dim3(grid), dim3(256), lds, s, a);
+        if (six)
+            hipLaunchKernelGGL((k_sieve<256, 6, U24>), dim3(grid), dim3(256), lds, s, a);
+        else
+            hipLaunchKernelGGL((k_sieve<256, 4, U24>), dim3(grid), dim3(256), lds, s, a);
         break;
     case 512:
-        hipLaunchKernelGGL((k_sieve<512, U24>), dim3(grid), dim3(512), lds, s, a);
+        if (six)
+            hipLaunchKernelGGL((k_sieve<512, 6, U24>), dim3(grid), dim3(512), lds, s, a);
+        else
+            hipLaunchKernelGGL((k_sieve<512, 4, U24>), dim3(grid), dim3(512), lds, s, a);
         break;
     case 1024:
-        hipLaunchKernelGGL((k_sieve<1024, U24>), dim3(grid), dim3(1024), lds, s, a);
+        hipLaunchKernelGGL((k_sieve<1024, 4, U24>), dim3(grid), dim3(1024), lds, s, a);
         break;
     default:
         return hipErrorInvalidValue;
@@ -1270,11 +1422,14 @@ hipError_t launch_sieve_t(const SieveArgs &a, uint32_t nt, uint32_t grid, size_t
 }  // namespace
 
 // u24: the caller guarantees that every prime a tile of the job uses is
-// below 2^24 - 8 (isqrt(hi - 1) below that for every range).
-hipError_t launch_sieve(const SieveArgs &a, uint32_t nt, uint32_t grid, bool u24, hipStream_t s)
+// below 2^24 - 8 (isqrt(hi - 1) below that for every range).  wg_per_cu:
+// resident workgroups per CU; with 24 or more waves per CU (six per SIMD)
+// the kernel variant holding 80 VGPRs (a smaller carried state) is used.
+hipError_t launch_sieve(const SieveArgs &a, uint32_t nt, uint32_t wg_per_cu, uint32_t grid, bool u24, hipStream_t s)
 {
     const size_t lds = (size_t)a.pw * 8 + sizeof(TileShared);  // planes, then bookkeeping
-    return u24 ? launch_sieve_t<true>(a, nt, grid, lds, s) : launch_sieve_t<false>(a, nt, grid, lds, s);
+    const bool six = nt < 1024 && (nt / 64) * wg_per_cu >= 24;
+    return u24 ? launch_sieve_t<true>(a, nt, six, grid, lds, s) : launch_sieve_t<false>(a, nt, six, grid, lds, s);
 }
 
 hipError_t launch_finalize(const FinalizeArgs &a, uint32_t grid, hipStream_t s)

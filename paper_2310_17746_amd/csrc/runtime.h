@@ -66,6 +66,7 @@ struct sieve_ctx {
     uint64_t limit = 0;
     std::vector<uint32_t> h_primes;
     sieve::rt::DevBuf<sieve::PrimeConst> d_prm;
+    sieve::rt::DevBuf<uint2> d_prd;  // the same primes as {P, offset of A_five hits from A_one hits}
     sieve::rt::DevBuf<uint32_t> d_pidx;
     sieve::rt::DevBuf<uint2> d_items;
     sieve::rt::DevBuf<uint32_t> d_item_prefix;

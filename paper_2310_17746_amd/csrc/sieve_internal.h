@@ -36,6 +36,7 @@ constexpr uint32_t kBucketMinPrimes = 32768; // fewest large primes worth a buck
 constexpr uint32_t kBucketKeep = 4;          // hits per thread the bucket fill replays from LDS
 constexpr uint32_t kPartPrimes = 262144;     // fewest primes (beyond the split items) per part of a split tile
 constexpr uint32_t kStaticMaxRanges = 1024;  // ranges per call of the allocation-free batch count
+constexpr uint32_t kMaxStrip = 64;           // tiles per strip (carried indices stay below 2^32 - 2^26)
 
 // One range of a job.  Host-computed plan; read-only on the device.
 struct RangeDesc {
@@ -61,6 +62,9 @@ struct RangeDesc {
     uint32_t nparts;     // work units per tile: 1, or the parts of a split tile
     uint32_t gtile0;     // split ranges: first global-bitmap slot (one per tile)
     uint32_t part_primes;  // split ranges: primes beyond the split items per part
+    uint32_t strip;      // tiles per strip: a workgroup sieves a strip's tiles in order and
+                         // carries each prime's next hit from tile to tile (1 for split ranges)
+    uint32_t nstrips;    // strips of this range: ceil(ntiles / strip)
 };
 
 // Per-job scalars, in device memory so that a captured graph can be replayed
@@ -77,7 +81,7 @@ struct JobHeader {
     int32_t elem_bytes;  // 4 or 8
     int32_t pad;
     uint64_t nseg;       // scan segments over all list ranges
-    uint64_t nvisit;     // sieve work units: tiles times their parts, over all ranges
+    uint64_t nvisit;     // sieve work units: strips (or tiles times their parts), over all ranges
     uint64_t gtiles;     // tiles of split ranges (global-bitmap slots)
     uint64_t gwords;     // words of those slots (2 planes each)
 };
@@ -116,6 +120,7 @@ struct SieveArgs {
     unsigned long long *counters;
     unsigned long long *counts;   // per range
     const PrimeConst *prm;        // every resident prime >= 5, ascending
+    const uint2 *prd;             // the same primes as {P, offset of A_five hits from A_one hits}
     const uint32_t *pidx;         // pidx[s] = number of resident primes <= 64 * s
     uint32_t pidx_len;
     uint32_t nprimes;

@@ -289,6 +289,13 @@ def test_error_paths(sv):
     dict(dense_hits=2000, cofactor_skip=pkg.SKIP_ALL),          # fixed-mask beside the skip path
     dict(split_hits=8),                                         # dense lane counts up to 384
     dict(segment_bytes=159744, split_hits=8),                   # dense lane counts up to 1184
+    # strips: primes carried from tile to tile in registers
+    dict(strip_tiles=1),                                        # every tile starts afresh
+    dict(strip_tiles=2, segment_bytes=8192),                    # many short strips
+    dict(strip_tiles=7, segment_bytes=16384, block_threads=256),  # registers and fresh starts
+    dict(strip_tiles=64, segment_bytes=8192, block_threads=512),  # longest strips
+    dict(strip_tiles=3, segment_bytes=16384, bucket_threshold=70000),  # strips beside buckets
+    dict(strip_tiles=5, segment_bytes=32768, cofactor_skip=pkg.SKIP_ALL, dense_hits=pkg.DENSE_NEVER),
 ])
 def test_parameter_grid_parity(params):
     with pkg.Sieve(0, params) as s:
