@@ -66,11 +66,6 @@ def first_multiple_index(P: int, base: int, M: int, r: int) -> int:
     return (v - base - r) // 6
 
 
-def sieve_start(P: int, base: int) -> int:
-    """Starting value for prime P in a chunk: max(P*P, base) (Sec. 1.1, Sec. 2.4)."""
-    return max(P * P, base)
-
-
 def count_coprime6(n: int) -> int:
     """#{1 <= m <= n : gcd(m, 6) = 1} for n >= 0."""
     if n <= 0:
@@ -94,3 +89,29 @@ def mark_count(P: int, lo: int, hi: int) -> int:
     if m_hi < m_lo:
         return 0
     return count_coprime6(m_hi) - count_coprime6(m_lo - 1)
+
+
+def mark_count_sum(primes, lo: int, hi: int) -> int:
+    """Sum of mark_count(P, lo, hi) over an array of primes (numpy, int64).
+
+    The same closed form, evaluated for every prime at once: cofactors m in
+    [ceil(max(P*P, lo) / P), floor((hi - 1) / P)] counted by count_coprime6.
+    Needs P*P and hi below 2^63.
+    """
+    import numpy as np
+
+    P = np.asarray(primes, dtype=np.int64)
+    if P.size == 0 or hi <= lo:
+        return 0
+    assert int(P.max()) < 3037000499 and hi < 2 ** 63
+    start = np.maximum(P * P, np.int64(lo))
+    m_lo = -(-start // P)
+    m_hi = (np.int64(hi) - 1) // P
+
+    def c6(n):
+        n = np.maximum(n, 0)
+        q, s = np.divmod(n, 6)
+        return 2 * q + (s >= 1) + (s >= 5)
+
+    ok = (start < hi) & (m_hi >= m_lo)
+    return int(np.sum(np.where(ok, c6(m_hi) - c6(m_lo - 1), 0)))

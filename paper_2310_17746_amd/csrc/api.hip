@@ -25,7 +25,7 @@
 namespace sieve {
 hipError_t set_sieve_lds_limit(uint32_t bytes);
 hipError_t launch_zero(const JobHeader *job, unsigned long long *counters, unsigned long long *counts,
-                       uint32_t *bcount, uint32_t *gbm, uint32_t *garrive, hipStream_t s);
+                       uint32_t *bcount, uint32_t *gbm, uint32_t *garrive, unsigned long long *tally, hipStream_t s);
 hipError_t launch_bucket(const BucketArgs &a, int pass, uint32_t cus, hipStream_t s);
 hipError_t launch_bucket_scan(const BucketScanArgs &a, hipStream_t s);
 hipError_t launch_sieve(const SieveArgs &a, uint32_t nt, uint32_t wg_per_cu, uint32_t grid, bool u24, hipStream_t s);
@@ -582,6 +582,16 @@ int ensure_capacity(sieve_ctx *c, uint64_t nranges, uint64_t nchunks, uint64_t n
             return SIEVE_E_NOMEM;
         changed = true;
     }
+#ifdef SIEVE_MARK_COUNT
+    if (!c->d_tally.p) {
+        if (!c->d_tally.reserve(4) ||
+            hipHostMalloc((void **)&c->h_tally, 4 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return SIEVE_E_NOMEM;
+        }
+        changed = true;
+    }
+#endif
     if (!c->d_counters.p) {
         if (!c->d_counters.reserve(kNumCounters))
             return SIEVE_E_NOMEM;
@@ -631,14 +641,15 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed, boo
     b.span = 192ull * pw;
     b.span_rcp = UINT64_MAX / b.span;
     b.win = c->bucket_win ? c->bucket_win : kBucketWindow;
+    b.tally = c->d_tally.p;  // allocated in the debug build only
     const uint32_t bcus = (uint32_t)c->cus;
     if (phase != kPhaseRest) {
         if (timed && phase == kPhaseBucketCount && (e = hipEventRecord(c->ev[3], s)) != hipSuccess)
             return e;
         // per-tile counts (exact layout) or cursors (estimated layout) start at 0
         uint32_t *bzero = phase == kPhaseDirect ? c->d_bcursor.p : c->d_bcount.p;
-        if ((e = launch_zero(job, c->d_counters.p, c->d_counts.p, bzero, c->d_gbm.p, c->d_garrive.p, s)) !=
-            hipSuccess)
+        if ((e = launch_zero(job, c->d_counters.p, c->d_counts.p, bzero, c->d_gbm.p, c->d_garrive.p, c->d_tally.p,
+                             s)) != hipSuccess)
             return e;
     }
     if (phase == kPhaseBucketCount) {
@@ -695,6 +706,7 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed, boo
     a.boff = c->d_boff.p;
     a.bcount = c->d_bcount.p;
     a.bcursor = c->d_bcursor.p;
+    a.tally = c->d_tally.p;
     if (timed && (e = hipEventRecord(c->ev[0], s)) != hipSuccess)
         return e;
     e = launch_sieve(a, c->prm.block_threads, c->prm.wg_per_cu, (uint32_t)c->cus * c->prm.wg_per_cu,
@@ -884,6 +896,10 @@ int run_job_once(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *h
         if (f == hipSuccess)
             f = hipMemcpyAsync(c->h_flag, c->d_counters.p + kErrorFlag, 2 * sizeof(unsigned long long),
                                hipMemcpyDeviceToHost, s);
+#ifdef SIEVE_MARK_COUNT
+        if (f == hipSuccess)
+            f = hipMemcpyAsync(c->h_tally, c->d_tally.p, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+#endif
         if (f == hipSuccess)
             f = hipStreamSynchronize(s);
         return f;
@@ -938,6 +954,10 @@ int run_job_once(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *h
         return hip_status(e);
     if (c->h_flag[0])
         return SIEVE_E_DEVICE;  // a kernel refused to run (see its error flag)
+#ifdef SIEVE_MARK_COUNT
+    for (int q = 0; q < 4; ++q)
+        c->tally_total[q] += c->h_tally[q];
+#endif
     if (c->timing && !use_graph) {
         float ta = 0, tb = 0, bc = 0, bf = 0;
         if (hipEventElapsedTime(&ta, c->ev[0], c->ev[1]) == hipSuccess &&
@@ -1133,6 +1153,9 @@ void destroy_ctx(sieve_ctx *c)
         (void)hipHostFree(c->h_status);
     if (c->h_flag)
         (void)hipHostFree(c->h_flag);
+    c->d_tally.release();
+    if (c->h_tally)
+        (void)hipHostFree(c->h_tally);
     for (auto &ev : c->ev)
         if (ev)
             (void)hipEventDestroy(ev);
@@ -1479,7 +1502,7 @@ int sieve_count_batch_static(sieve_ctx *ctx, const uint64_t *lo, const uint64_t 
                            hipMemcpyHostToDevice, s);
     // counters and counts start at zero (a kernel clears them)
     if (e == hipSuccess)
-        e = launch_zero(job, counters, dcounts, nullptr, nullptr, nullptr, s);
+        e = launch_zero(job, counters, dcounts, nullptr, nullptr, nullptr, nullptr, s);
     if (e == hipSuccess) {
         SieveArgs a;
         memset(&a, 0, sizeof a);
@@ -1580,6 +1603,20 @@ int sieve_plan_range(uint64_t lo, uint64_t hi, uint32_t segment_bytes, uint64_t 
     plan_range(lo, hi, segment_bytes / 8, *ntiles, *base, *last_words);
     return SIEVE_OK;
 }
+
+#ifdef SIEVE_MARK_COUNT
+int sieve_debug_tally(sieve_ctx *ctx, uint64_t *out, int reset)
+{
+    if (!ctx || !out)
+        return SIEVE_E_INVAL;
+    for (int q = 0; q < 4; ++q) {
+        out[q] = ctx->tally_total[q];
+        if (reset)
+            ctx->tally_total[q] = 0;
+    }
+    return SIEVE_OK;
+}
+#endif
 
 int sieve_set_timing(sieve_ctx *ctx, int on)
 {

@@ -86,15 +86,68 @@ __device__ __forceinline__ void lds_or(uint32_t byte_addr, uint32_t mask)
     __atomic_fetch_or((lds_u32 *)(size_t)byte_addr, mask, __ATOMIC_RELAXED);
 }
 
+// Marking tally of the debug build (SIEVE_MARK_COUNT), per thread: the hits
+// the marking loops visit (whether they issue the OR or skip it because the
+// cofactor is a multiple of 5, which the presieve has cleared), the ORs
+// issued, the hits skipped, and the runs whose first hit is not a multiple of
+// its prime at or past the prime's square.  In the product build the struct
+// is empty and every call compiles to nothing.
+struct MarkTally {
+#ifdef SIEVE_MARK_COUNT
+    unsigned long long hits = 0, issued = 0, skipped = 0, bad = 0;
+    __device__ __forceinline__ void op() { ++issued; }
+    __device__ __forceinline__ uint64_t run(uint32_t start, uint32_t step, uint32_t end)
+    {
+        const uint64_t h = start < end ? ((uint64_t)end - start + step - 1) / step : 0;
+        hits += h;
+        return h;
+    }
+    __device__ __forceinline__ void skip(uint64_t n) { skipped += n; }
+    __device__ __forceinline__ void check(uint64_t B, uint32_t i, uint32_t r, uint32_t P)
+    {
+        const uint64_t v = B + 6ull * i + r;
+        if (v % P != 0 || v < (uint64_t)P * P)
+            ++bad;
+    }
+#else
+    __device__ __forceinline__ void op() {}
+    __device__ __forceinline__ uint64_t run(uint32_t, uint32_t, uint32_t) { return 0; }
+    __device__ __forceinline__ void skip(uint64_t) {}
+    __device__ __forceinline__ void check(uint64_t, uint32_t, uint32_t, uint32_t) {}
+#endif
+};
+
+#ifdef SIEVE_MARK_COUNT
+// Adds a thread's tally to the job's four counters (wavefront sums first).
+__device__ inline void tally_flush(const MarkTally &t, unsigned long long *out)
+{
+    unsigned long long v[4] = {t.hits, t.issued, t.skipped, t.bad};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        for (int d = 32; d >= 1; d >>= 1)
+            v[q] += __shfl_xor(v[q], d, 64);
+        if ((threadIdx.x & 63) == 0 && v[q])
+            atomicAdd(&out[q], v[q]);
+    }
+}
+#endif
+
+__device__ __forceinline__ void lds_or(uint32_t byte_addr, uint32_t mask, MarkTally &t)
+{
+    t.op();
+    lds_or(byte_addr, mask);
+}
+
 // Sets the composite bits start, start + step, ... below end of the plane
 // bit array (A_one bits from 0, A_five bits from 32 pw) and returns the first
 // index at or past end, where the next tile's hits continue.  The paper
 // strides by P indices in each array (Sec. 3: adding P to the index adds 6P
 // to the value and keeps the residue mod 6).
-__device__ __forceinline__ uint32_t mark_run(uint32_t i, uint32_t step, uint32_t end)
+__device__ __forceinline__ uint32_t mark_run(uint32_t i, uint32_t step, uint32_t end, MarkTally &t)
 {
     if (i >= end)
         return i;
+    (void)t.run(i, step, end);
     if (step < (end >> 2)) {
         const uint32_t lim = end - 3 * step;  // i < lim keeps i + 3*step < end
         while (i < lim) {
@@ -102,25 +155,26 @@ __device__ __forceinline__ uint32_t mark_run(uint32_t i, uint32_t step, uint32_t
             // stops the compiler from splitting it into several).
             asm volatile("" : "+v"(i));
             const uint32_t i1 = i + step, i2 = i1 + step, i3 = i2 + step;
-            lds_or((i >> 3) & ~3u, 1u << (i & 31));
-            lds_or((i1 >> 3) & ~3u, 1u << (i1 & 31));
-            lds_or((i2 >> 3) & ~3u, 1u << (i2 & 31));
-            lds_or((i3 >> 3) & ~3u, 1u << (i3 & 31));
+            lds_or((i >> 3) & ~3u, 1u << (i & 31), t);
+            lds_or((i1 >> 3) & ~3u, 1u << (i1 & 31), t);
+            lds_or((i2 >> 3) & ~3u, 1u << (i2 & 31), t);
+            lds_or((i3 >> 3) & ~3u, 1u << (i3 & 31), t);
             i = i3 + step;
         }
     }
     for (; i < end; i += step)
-        lds_or((i >> 3) & ~3u, 1u << (i & 31));
+        lds_or((i >> 3) & ~3u, 1u << (i & 31), t);
     return i;
 }
 
 // As mark_plane for a step that is a multiple of 32 bits: every hit then
 // sits at the same bit of its word, so the mask is fixed and the LDS byte
 // address advances by step / 8.  One add per mark.
-__device__ __forceinline__ void mark_plane_fixed(uint32_t start, uint32_t step, uint32_t nbits)
+__device__ __forceinline__ void mark_plane_fixed(uint32_t start, uint32_t step, uint32_t nbits, MarkTally &t)
 {
     if (start >= nbits)
         return;
+    (void)t.run(start, step, nbits);
     const uint32_t mask = 1u << (start & 31);
     const uint32_t end = nbits >> 3;  // nbits is a whole number of words
     const uint32_t sb = step >> 3;
@@ -129,15 +183,15 @@ __device__ __forceinline__ void mark_plane_fixed(uint32_t start, uint32_t step, 
         const uint32_t lim = end - 3 * sb;  // a < lim keeps a + 3*sb < end
         while (a < lim) {
             asm volatile("" : "+v"(a));
-            lds_or(a, mask);
-            lds_or(a + sb, mask);
-            lds_or(a + 2 * sb, mask);
-            lds_or(a + 3 * sb, mask);
+            lds_or(a, mask, t);
+            lds_or(a + sb, mask, t);
+            lds_or(a + 2 * sb, mask, t);
+            lds_or(a + 3 * sb, mask, t);
             a += 4 * sb;
         }
     }
     for (; a < end; a += sb)
-        lds_or(a, mask);
+        lds_or(a, mask, t);
 }
 
 // As mark_plane, for a lane whose hits n = 0, 1, 2, ... have cofactors
@@ -145,10 +199,15 @@ __device__ __forceinline__ void mark_plane_fixed(uint32_t start, uint32_t step, 
 // n = s (mod 5): those values are multiples of 5, already cleared by the
 // presieve, so a fifth of the LDS operations is saved.  s in 0..4.
 __device__ __forceinline__ void mark_plane_skip5(uint32_t base, uint64_t start, uint32_t step, uint32_t nbits,
-                                                 uint32_t s)
+                                                 uint32_t s, MarkTally &t)
 {
     if (start >= nbits)
         return;
+    {
+        // hits n = s, s + 5, ... of the run are skipped
+        const uint64_t h = t.run((uint32_t)start, step, nbits);
+        t.skip(h > s ? (h - s - 1) / 5 + 1 : 0);
+    }
     uint32_t i = (uint32_t)start;
     if (step < nbits / 5) {
         // kept offsets of one period of five hits
@@ -161,10 +220,10 @@ __device__ __forceinline__ void mark_plane_skip5(uint32_t base, uint64_t start, 
         while (i < lim) {
             asm volatile("" : "+v"(i));
             const uint32_t i0 = i + o0, i1 = i + o1, i2 = i + o2, i3 = i + o3;
-            lds_or(((i0 >> 3) & ~3u) + base, 1u << (i0 & 31));
-            lds_or(((i1 >> 3) & ~3u) + base, 1u << (i1 & 31));
-            lds_or(((i2 >> 3) & ~3u) + base, 1u << (i2 & 31));
-            lds_or(((i3 >> 3) & ~3u) + base, 1u << (i3 & 31));
+            lds_or(((i0 >> 3) & ~3u) + base, 1u << (i0 & 31), t);
+            lds_or(((i1 >> 3) & ~3u) + base, 1u << (i1 & 31), t);
+            lds_or(((i2 >> 3) & ~3u) + base, 1u << (i2 & 31), t);
+            lds_or(((i3 >> 3) & ~3u) + base, 1u << (i3 & 31), t);
             i += 5 * step;
         }
     }
@@ -173,7 +232,7 @@ __device__ __forceinline__ void mark_plane_skip5(uint32_t base, uint64_t start, 
         if (x >= nbits)
             break;
         if (n != s)
-            lds_or((((uint32_t)x >> 3) & ~3u) + base, 1u << ((uint32_t)x & 31));
+            lds_or((((uint32_t)x >> 3) & ~3u) + base, 1u << ((uint32_t)x & 31), t);
     }
 }
 
@@ -266,6 +325,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W))) k_
 {
     constexpr int K = reg_primes<W>();
     extern __shared__ uint32_t lds[];
+    MarkTally tally;
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1);
     const uint32_t wave = tid / kWave;
@@ -325,8 +385,13 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W))) k_
         if (tid < 64)
             sh.chunk[tid] = 0;
         __syncthreads();
-        if (!sh.ok)
+        if (!sh.ok) {
+#ifdef SIEVE_MARK_COUNT
+            if (a.tally)
+                tally_flush(tally, a.tally);
+#endif
             break;
+        }
         const uint32_t rix = sh.range;
         const RangeDesc &d = a.ranges[rix];
         const uint32_t k0 = sh.k0, k1 = sh.k1, part = sh.part;
@@ -457,10 +522,14 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W))) k_
                                 step = g * pc.p;
                                 off = j * pc.p;
                             }
+                            if (id1t + off < nbits)
+                                tally.check(B, id1t + off, 1, pc.p);
+                            if (id5t + off < nbits)
+                                tally.check(B, id5t + off, 5, pc.p);
                             if (v < n_dense) {
                                 // g is a multiple of 32: fixed-mask marking
-                                mark_plane_fixed(id1t + off, step, nbits);
-                                mark_plane_fixed(id5t + off + off5, step, nbits + off5);
+                                mark_plane_fixed(id1t + off, step, nbits, tally);
+                                mark_plane_fixed(id5t + off + off5, step, nbits + off5, tally);
                             } else if (a.skip5 == 1 || (a.skip5 == 2 && v < n_items)) {
                                 // hit n of this lane has cofactor m0 + 6(j + n g) = c + n g (mod 5);
                                 // it is a multiple of 5 when n = -c / g (mod 5)
@@ -468,11 +537,12 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W))) k_
                                 const uint32_t ginv = inv_mod5(g);
                                 const uint32_t c1 = (cofactor_mod5(b5, id1t, 1, inv5) + j) % 5u;
                                 const uint32_t c5 = (cofactor_mod5(b5, id5t, 0, inv5) + j) % 5u;
-                                mark_plane_skip5(0, id1t + off, step, nbits, ((5u - c1) * ginv) % 5u);
-                                mark_plane_skip5(0, id5t + off + off5, step, nbits + off5, ((5u - c5) * ginv) % 5u);
+                                mark_plane_skip5(0, id1t + off, step, nbits, ((5u - c1) * ginv) % 5u, tally);
+                                mark_plane_skip5(0, id5t + off + off5, step, nbits + off5, ((5u - c5) * ginv) % 5u,
+                                                 tally);
                             } else {
-                                (void)mark_run(id1t + off, step, nbits);
-                                (void)mark_run(id5t + off + off5, step, nbits + off5);
+                                (void)mark_run(id1t + off, step, nbits, tally);
+                                (void)mark_run(id5t + off + off5, step, nbits + off5, tally);
                             }
                         }
                     }
@@ -505,14 +575,21 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W))) k_
                                 // square before the tile: x1 < P; (x1 + dlt) mod P
                                 // without overflowing 32 bits
                                 const uint32_t x5 = x1 >= p - dlt ? x1 - (p - dlt) : x1 + dlt;
-                                if (x5 < nbits)
-                                    (void)mark_run(x5 + off5, p, nbits + off5);
-                                if (x1 < nbits)
-                                    x1 = mark_run(x1, p, nbits);
+                                if (x5 < nbits) {
+                                    tally.check(B, x5, 5, p);
+                                    (void)mark_run(x5 + off5, p, nbits + off5, tally);
+                                }
+                                if (x1 < nbits) {
+                                    tally.check(B, x1, 1, p);
+                                    x1 = mark_run(x1, p, nbits, tally);
+                                }
                             } else if (x1 < nbits) {
                                 // the square lies in this tile: both progressions start there
-                                (void)mark_run(x1 + dlt + off5, p, nbits + off5);
-                                x1 = mark_run(x1, p, nbits);
+                                tally.check(B, x1, 1, p);
+                                if (x1 + dlt < nbits)
+                                    tally.check(B, x1 + dlt, 5, p);
+                                (void)mark_run(x1 + dlt + off5, p, nbits + off5, tally);
+                                x1 = mark_run(x1, p, nbits, tally);
                             }
                             id1[jj] = x1 - nbits_full;
                         }
@@ -529,7 +606,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W))) k_
                             const uint32_t v = a.bdata[e0 + e];
                             const uint32_t bit = v & 0x7FFFFFFFu;
                             if (bit < nbits)
-                                lds_or(((bit >> 3) & ~3u) + ((v >> 31) ? base5 : 0u), 1u << (bit & 31));
+                                lds_or(((bit >> 3) & ~3u) + ((v >> 31) ? base5 : 0u), 1u << (bit & 31), tally);
                         }
                     }
                 }
@@ -571,10 +648,20 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W))) k_
                         else
                             tile_start(pc, sqb, Bm1, B32, narrow, id1t, id5t);
                         // i < nbits < 2^20 and P < 2^32 - 2^20: i + P does not wrap
-                        for (uint32_t i = id1t; i < nbits; i += pc.p)
+                        if (id1t < nbits)
+                            tally.check(B, id1t, 1, pc.p);
+                        if (id5t < nbits)
+                            tally.check(B, id5t, 5, pc.p);
+                        (void)tally.run(id1t, pc.p, nbits);
+                        (void)tally.run(id5t, pc.p, nbits);
+                        for (uint32_t i = id1t; i < nbits; i += pc.p) {
+                            tally.op();
                             atomicOr(&g1[i >> 5], 1u << (i & 31));
-                        for (uint32_t i = id5t; i < nbits; i += pc.p)
+                        }
+                        for (uint32_t i = id5t; i < nbits; i += pc.p) {
+                            tally.op();
                             atomicOr(&g5[i >> 5], 1u << (i & 31));
+                        }
                     }
                 }
             }
@@ -824,6 +911,7 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket(BucketArgs a)
     const uint64_t nunits = a.job->nunits;
     const uint32_t nranges = a.job->nranges;
     const uint32_t nbits = a.nbits;
+    MarkTally tally;
 
     uint32_t r = 0;
     uint64_t r_end = 0;  // one past the last unit of range r
@@ -840,6 +928,18 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket(BucketArgs a)
         const uint32_t wend = (d.ntiles - w0) < kBucketWindow ? d.ntiles : w0 + kBucketWindow;
         const uint32_t k = d.kbig + blk * kBucketThreads + tid;
         HitWalk w = walk_init(a, d, k, w0, wend);
+#ifdef SIEVE_MARK_COUNT
+        // hits past the range's last plane word are binned but never applied
+        const uint32_t lastbits = 32u * d.last_words;
+        auto covered = [&](uint32_t tt, uint32_t bb) { return tt + 1 < d.ntiles || bb < lastbits; };
+        if (PASS != 0 && k < d.nact) {
+            const uint32_t P = a.prm[k].p;
+            if (w.t1 < wend && covered(w.t1, w.b1))
+                tally.check(d.base + (uint64_t)w.t1 * a.span, w.b1, 1, P);
+            if (w.t5 < wend && covered(w.t5, w.b5))
+                tally.check(d.base + (uint64_t)w.t5 * a.span, w.b5, 5, P);
+        }
+#endif
         for (uint32_t i = tid; i < wend - w0; i += kBucketThreads)
             s_cnt[i] = 0;
         __syncthreads();
@@ -863,6 +963,12 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket(BucketArgs a)
             {
                 HitWalk c = w;  // count first, without moving the walk
                 while (c.t1 < wend) {
+#ifdef SIEVE_MARK_COUNT
+                    if (covered(c.t1, c.b1)) {
+                        tally.hits++;
+                        tally.skipped += c.c1 == 0;
+                    }
+#endif
                     if (c.c1) {
                         atomicAdd(&s_cnt[c.t1 - w0], 1u);
                         if (nk < kBucketKeep)
@@ -872,6 +978,12 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket(BucketArgs a)
                     walk_step(c.t1, c.b1, c.c1, c, nbits);
                 }
                 while (c.t5 < wend) {
+#ifdef SIEVE_MARK_COUNT
+                    if (covered(c.t5, c.b5)) {
+                        tally.hits++;
+                        tally.skipped += c.c5 == 0;
+                    }
+#endif
                     if (c.c5) {
                         atomicAdd(&s_cnt[c.t5 - w0], 1u);
                         if (nk < kBucketKeep)
@@ -932,6 +1044,12 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket(BucketArgs a)
         }
         __syncthreads();
     }
+#ifdef SIEVE_MARK_COUNT
+    if (PASS != 0 && a.tally)
+        tally_flush(tally, a.tally);
+#else
+    (void)tally;
+#endif
 }
 
 // Exclusive scan of the per-tile bucket counts (one workgroup); also clears
@@ -1297,13 +1415,15 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(CompactArgs a)
 }
 
 __global__ void k_zero(const JobHeader *job, unsigned long long *counters, unsigned long long *counts,
-                       uint32_t *bcount, uint32_t *gbm, uint32_t *garrive)
+                       uint32_t *bcount, uint32_t *gbm, uint32_t *garrive, unsigned long long *tally)
 {
     const uint32_t n = job->nranges;
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t stride = gridDim.x * blockDim.x;
     if (g < kNumCounters)
         counters[g] = 0;
+    if (tally && g < 4)
+        tally[g] = 0;
     for (uint32_t i = g; i < n; i += stride)
         counts[i] = 0;
     if (job->nunits)
@@ -1335,9 +1455,9 @@ hipError_t set_sieve_lds_limit(uint32_t segment_bytes)
 }
 
 hipError_t launch_zero(const JobHeader *job, unsigned long long *counters, unsigned long long *counts,
-                       uint32_t *bcount, uint32_t *gbm, uint32_t *garrive, hipStream_t s)
+                       uint32_t *bcount, uint32_t *gbm, uint32_t *garrive, unsigned long long *tally, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_zero, dim3(256), dim3(256), 0, s, job, counters, counts, bcount, gbm, garrive);
+    hipLaunchKernelGGL(k_zero, dim3(256), dim3(256), 0, s, job, counters, counts, bcount, gbm, garrive, tally);
     return hipGetLastError();
 }
 

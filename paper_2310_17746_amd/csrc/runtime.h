@@ -128,6 +128,14 @@ struct sieve_ctx {
     hipStream_t copy_stream = nullptr;
     hipEvent_t piece_ev[2] = {nullptr, nullptr};
 
+    // Marking tally of the debug build (SIEVE_MARK_COUNT): device counters of
+    // the current job (hits, ORs issued, hits skipped, bad runs), a pinned
+    // copy, and the sums over the jobs since the last reset.  Unallocated in
+    // the product build.
+    sieve::rt::DevBuf<unsigned long long> d_tally;
+    unsigned long long *h_tally = nullptr;
+    unsigned long long tally_total[4] = {0, 0, 0, 0};
+
     // Device address of this GPU's fixed scratch array (allocation-free
     // entry point), looked up once when the context is created.
     unsigned char *static_scratch = nullptr;

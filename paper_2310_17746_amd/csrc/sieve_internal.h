@@ -143,6 +143,7 @@ struct SieveArgs {
     const uint32_t *bcursor;      // estimated layout, per tile: entries written
     uint32_t *gbm;                // split tiles: both planes per slot (2 pw words), zeroed per job
     uint32_t *garrive;            // split tiles: parts finished, per slot, zeroed per job
+    unsigned long long *tally;    // debug build only: hits, ORs issued, hits skipped, bad runs
 };
 
 // Bucket sieve (large primes of multi-tile ranges).  One work unit is a block
@@ -163,6 +164,7 @@ struct BucketArgs {
     uint64_t span_rcp;            // floor((2^64 - 1) / span)
     uint32_t win;                 // LDS bins per workgroup: >= the tiles of every unit's window
     uint32_t pad;
+    unsigned long long *tally;    // debug build only, as in SieveArgs
 };
 
 struct BucketScanArgs {

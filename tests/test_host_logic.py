@@ -22,21 +22,29 @@ pkg = pytest.importorskip("paper_2310_17746_amd")
 
 
 def _declared_functions():
-    names = set()
+    names = {}
     inc = os.path.join(ROOT, "include")
     for fn in sorted(os.listdir(inc)):
         if fn.endswith(".h"):
             hdr = re.sub(r"/\*.*?\*/", "", open(os.path.join(inc, fn)).read(), flags=re.S)
-            names |= set(re.findall(r"\b(sieve_[a-z_0-9]+)\s*\(", hdr))
-    return sorted(names)
+            names[fn] = sorted(set(re.findall(r"\b(sieve_[a-z_0-9]+)\s*\(", hdr)))
+    return names
 
 
 def test_library_exports_every_declared_symbol():
+    """libsieve.so exports every function of the product headers; the
+    mark-counting build exports those and sieve_debug.h's as well."""
+    import ctypes
     lib = pkg.load_library()
+    dbg = ctypes.CDLL(os.path.join(ROOT, "paper_2310_17746_amd", "libsieve_markcount.so"))
     names = _declared_functions()
-    assert "sieve_count" in names and "sieve_list_batch" in names
-    for name in names:
+    product = [n for fn, ns in names.items() if fn != "sieve_debug.h" for n in ns]
+    assert "sieve_count" in product and "sieve_list_batch" in product
+    assert names["sieve_debug.h"] == ["sieve_debug_tally"]
+    for name in product:
         assert hasattr(lib, name), name
+        assert hasattr(dbg, name), name
+    assert hasattr(dbg, "sieve_debug_tally") and not hasattr(lib, "sieve_debug_tally")
 
 
 def test_worked_example_through_library():

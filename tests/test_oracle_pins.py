@@ -201,6 +201,12 @@ def test_mark_count_closed_form():
         direct = sum(1 for v in range(max(P * P, lo), hi)
                      if v % P == 0 and math.gcd(v // P, 6) == 1)
         assert wheel.mark_count(P, lo, hi) == direct
+    # The vectorised sum is the scalar closed form summed.
+    for _ in range(200):
+        ps = brute.primes_td(5, rng.choice([100, 2000, 20000]))
+        lo = rng.randrange(0, 10 ** 7)
+        hi = lo + rng.randrange(0, 10 ** 6)
+        assert wheel.mark_count_sum(ps, lo, hi) == sum(wheel.mark_count(P, lo, hi) for P in ps)
     # Only values coprime to 6 are ever cleared (Sec. 2.1).
     for P in (5, 7, 11):
         for v in range(P * P, 3000, P):
