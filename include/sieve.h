@@ -11,8 +11,8 @@
  *     (Sec. 2.2, 2.3), here one workgroup per segment ("tile");
  *   - each base prime P starts at max(P*P, segment start) (Sec. 1.1, 2.4),
  *     at the indices given by Table 1 (Sec. 3), and strides by P indices;
- *   - the survivors are counted, or listed in increasing order (Fig. 1,
- *     Fig. 4: "return all k such that mod1[k] or mod5[k]").
+ *   - the survivors are counted, or listed in increasing order (Fig. 1;
+ *     Fig. 4 outputs every index left unmarked in either array).
  * 2 and 3 lie outside the wheel and are reported when in range; 1 is not
  * prime and never reported.
  *
@@ -27,9 +27,20 @@
  *   - The caller owns every buffer it passes, host or device; the library
  *     never frees or retains them after the call returns.
  *   - `stream` arguments take a hipStream_t (for instance
- *     torch.cuda.current_stream().cuda_stream); NULL selects the context's
- *     own stream.  Work is ordered after earlier work on that stream, and the
- *     call returns when its work has finished (host outputs are then valid).
+ *     torch.cuda.current_stream().cuda_stream).  NULL selects the context's
+ *     own stream, and the call returns when its work has finished (host
+ *     outputs are then valid).  A non-NULL stream makes sieve_list,
+ *     sieve_count_batch and sieve_list_batch stream-ordered: the job is
+ *     enqueued after earlier work on that stream and the call returns; the
+ *     host outputs (counts, status, *n_out) are written when the stream
+ *     reaches the end of the job, so they are valid after the stream
+ *     synchronizes, and the caller keeps those host arrays alive until then.
+ *     A job that needs a host decision mid-way (ranges that take the bucket
+ *     sieve, whose estimated layout may have to be re-run exactly, and jobs
+ *     cut into pieces by the bucket budget) waits for its stream before
+ *     returning, with the outputs then valid.  Jobs of one context on
+ *     different streams run one after another (the context's scratch is
+ *     shared).
  *   - A context is not thread-safe, except for the sieve_server_* calls.
  */
 #ifndef SIEVE_H
@@ -165,8 +176,9 @@ int sieve_destroy(sieve_ctx *ctx);
 int sieve_get_params(const sieve_ctx *ctx, sieve_params *p);
 
 /*
- * Makes every prime <= limit resident on the device (Sec. 4: only primes up
- * to the square root are needed for sieving).  Grow-only and idempotent: a
+ * Makes every prime <= limit resident on the device: the Sieve Data Store of
+ * Sec. 4 (sieving a range needs the primes up to the square root of its
+ * end).  Grow-only and idempotent: a
  * smaller limit than the current one does nothing.  limit < 2^32.  The
  * primes beyond isqrt(limit) are produced by this library's own GPU list
  * path.  *n_out (optional) receives the number of resident primes >= 5.
@@ -177,33 +189,44 @@ int sieve_base_primes(sieve_ctx *ctx, uint64_t limit, uint64_t *n_out);
 int sieve_base_limit(const sieve_ctx *ctx, uint64_t *limit);
 
 /*
- * Number of primes in [lo, hi) into *count (host).  Synchronous, on the
- * context stream.
+ * Number of primes in [lo, hi) into *count (host): the primes of Fig. 1's
+ * problem over a segment range (Sec. 2.2), counted from the unmarked entries
+ * of A_one / A_five (Fig. 4) plus 2 and 3.  Synchronous, on the context
+ * stream.
  */
 int sieve_count(sieve_ctx *ctx, uint64_t lo, uint64_t hi, uint64_t *count);
 
 /*
- * Writes the primes of [lo, hi) in strictly increasing order to out_dev
- * (device memory owned by the caller, elem_bytes = 4 for uint32 or 8 for
- * uint64, little-endian, contiguous).  *n_out (required) receives the count.
- * If the count exceeds cap, nothing is guaranteed to be written, the call
- * returns SIEVE_E_CAPACITY and *n_out holds the required count.
- * elem_bytes = 4 needs hi - 1 <= 2^32 - 1, else SIEVE_E_DTYPE.
+ * Writes the primes of [lo, hi) in strictly increasing order to out_dev: the
+ * output of Fig. 1 (all primes of the range) as Fig. 4 produces it, every
+ * index left unmarked in either array in value order, here a contiguous
+ * array instead of the linked list of Sec. 4.  out_dev is device memory
+ * owned by the caller, elem_bytes = 4 for uint32 or 8 for uint64,
+ * little-endian, contiguous.  *n_out (required) receives the count.  If the
+ * count exceeds cap, nothing is guaranteed to be written and *n_out holds the
+ * required count; a synchronous call then returns SIEVE_E_CAPACITY, a
+ * stream-ordered one returns SIEVE_OK and the caller sees *n_out > cap after
+ * the stream synchronizes.  elem_bytes = 4 needs hi - 1 <= 2^32 - 1, else
+ * SIEVE_E_DTYPE.
  */
 int sieve_list(sieve_ctx *ctx, uint64_t lo, uint64_t hi, void *out_dev, uint64_t cap,
                int elem_bytes, uint64_t *n_out, void *stream);
 
 /*
  * Batched count over n ranges lo[i], hi[i] (host arrays) in one persistent
- * launch; counts[i] (host) receives the prime count of range i.  Any invalid
- * range fails the whole call before launch.
+ * launch: the segments of every range (Sec. 2.2) are the work units of one
+ * pool of workers (Sec. 2.3, Fig. 4's worker loop).  counts[i] (host)
+ * receives the prime count of range i.  Any invalid range fails the whole
+ * call before launch.
  */
 int sieve_count_batch(sieve_ctx *ctx, const uint64_t *lo, const uint64_t *hi, uint64_t n,
                       uint64_t *counts, void *stream);
 
 /*
- * Mixed batch.  For range i (host arrays): mode[i] = 0 counts, 1 also lists
- * the primes into out_dev at element offset off[i] with capacity cap[i]
+ * Mixed batch (Sec. 2.2-2.3 as for sieve_count_batch; listed ranges produce
+ * Fig. 4's output as sieve_list does).  For range i (host arrays): mode[i] =
+ * 0 counts, 1 also lists the primes into out_dev at element offset off[i]
+ * with capacity cap[i]
  * (elements of elem_bytes).  counts[i] (host) receives every range's count;
  * status[i] (host) receives SIEVE_OK or, for a list range that does not fit,
  * SIEVE_E_CAPACITY (its count is still reported; other ranges are not

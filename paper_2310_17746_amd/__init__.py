@@ -19,7 +19,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Sieve", "Server", "Generator", "SieveError", "Params", "list_bound", "wheel_start", "plan_range", "probe_lds",
+__all__ = ["Sieve", "Server", "Generator", "SieveError", "Params", "ListResult", "list_bound", "wheel_start", "plan_range", "probe_lds",
            "lib_path", "load_library", "SIEVE_OK", "SIEVE_E_CAPACITY", "SIEVE_E_LIMIT",
            "STATIC_MAX_RANGES"]
 
@@ -226,6 +226,33 @@ def _stream_handle(stream):
     return stream.cuda_stream
 
 
+def _sync(stream) -> None:
+    """Waits for a torch stream (or a raw hipStream_t handle)."""
+    torch = _torch()
+    if isinstance(stream, int):
+        stream = torch.cuda.ExternalStream(stream)
+    stream.synchronize()
+
+
+class ListResult:
+    """A stream-ordered list call: `out` is filled and `count` is valid once
+    the stream has reached the end of the job (after it synchronizes).  Keep
+    this object alive until then: the library writes the count into it."""
+
+    def __init__(self, out, stream):
+        self.out = out
+        self.stream = stream
+        self._n = _u64()
+
+    @property
+    def count(self) -> int:
+        return self._n.value
+
+    def primes(self):
+        """The filled prefix of `out` (after the stream has synchronized)."""
+        return self.out[: min(self._n.value, self.out.numel())]
+
+
 class Sieve:
     """A sieve context on one GPU (resident base primes, scratch, stream)."""
 
@@ -315,7 +342,24 @@ class Sieve:
         if code == SIEVE_E_CAPACITY:
             raise SieveError(code, "sieve_list needs %d elements" % n.value)
         _check(code, "sieve_list")
+        if stream is not None:
+            _sync(stream)  # the call was stream-ordered: n is written when the stream gets there
+            if n.value > out.numel():
+                raise SieveError(SIEVE_E_CAPACITY, "sieve_list needs %d elements" % n.value)
         return out[: n.value]
+
+    def list_async(self, lo: int, hi: int, out, elem_bytes: int, stream) -> "ListResult":
+        """Enqueues the list of [lo, hi) into `out` on `stream` and returns at
+        once (a job that needs the bucket sieve waits for the stream first).
+        The returned ListResult's count and primes() are valid after the
+        stream synchronizes; a count above out.numel() means nothing was
+        written."""
+        if out.element_size() != elem_bytes or not out.is_contiguous():
+            raise ValueError("out must be contiguous with %d-byte elements" % elem_bytes)
+        r = ListResult(out, stream)
+        _check(self._lib.sieve_list(self._h, lo, hi, out.data_ptr(), out.numel(), elem_bytes,
+                                    ctypes.byref(r._n), _stream_handle(stream)), "sieve_list")
+        return r
 
     def list_host(self, lo: int, hi: int, elem_bytes: int = 8, out=None, piece_elems: int = 0):
         """Primes of [lo, hi) streamed into host memory.
@@ -362,7 +406,10 @@ class Sieve:
             _check(code, "sieve_list")
         return n.value
 
-    def count_batch(self, lo, hi, stream=None) -> np.ndarray:
+    def count_batch(self, lo, hi, stream=None, sync: bool = True) -> np.ndarray:
+        """Counts of many ranges in one job.  With a stream and sync=False the
+        call is stream-ordered: the returned array is filled when the stream
+        reaches the end of the job (keep it until the stream synchronizes)."""
         lo = np.ascontiguousarray(lo, dtype=np.uint64)
         hi = np.ascontiguousarray(hi, dtype=np.uint64)
         if lo.shape != hi.shape:
@@ -371,6 +418,8 @@ class Sieve:
         _check(self._lib.sieve_count_batch(self._h, lo.ctypes.data, hi.ctypes.data, lo.size,
                                            counts.ctypes.data, _stream_handle(stream)),
                "sieve_count_batch")
+        if stream is not None and sync:
+            _sync(stream)
         return counts
 
     def count_batch_static(self, lo, hi, stream=None) -> np.ndarray:
@@ -386,8 +435,9 @@ class Sieve:
                "sieve_count_batch_static")
         return counts
 
-    def list_batch(self, lo, hi, mode, out, off, cap, elem_bytes: int = 8, stream=None):
-        """Mixed batch; returns (counts, status) as numpy arrays."""
+    def list_batch(self, lo, hi, mode, out, off, cap, elem_bytes: int = 8, stream=None, sync: bool = True):
+        """Mixed batch; returns (counts, status) as numpy arrays (with a stream
+        and sync=False: filled when the stream reaches the end of the job)."""
         lo = np.ascontiguousarray(lo, dtype=np.uint64)
         hi = np.ascontiguousarray(hi, dtype=np.uint64)
         mode = np.ascontiguousarray(mode, dtype=np.uint8)
@@ -401,6 +451,8 @@ class Sieve:
                                           n, optr, off.ctypes.data, cap.ctypes.data, elem_bytes,
                                           counts.ctypes.data, status.ctypes.data,
                                           _stream_handle(stream)), "sieve_list_batch")
+        if stream is not None and sync:
+            _sync(stream)
         return counts, status
 
     # -- measurement -------------------------------------------------------

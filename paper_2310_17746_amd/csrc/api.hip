@@ -513,6 +513,14 @@ uint64_t grow(uint64_t cur, uint64_t need, uint64_t floor_)
 int ensure_capacity(sieve_ctx *c, uint64_t nranges, uint64_t nchunks, uint64_t ntiles, uint64_t gtiles)
 {
     bool changed = false;
+    if (nranges > c->cap_ranges || nchunks > c->cap_chunks || ntiles > c->cap_tiles || gtiles > c->cap_gtiles) {
+        // Buffers are about to be replaced: earlier stream-ordered jobs, and
+        // their pending copies into the host slots, finish first.
+        if (hipDeviceSynchronize() != hipSuccess) {
+            (void)hipGetLastError();
+            return SIEVE_E_DEVICE;
+        }
+    }
     if (nranges > c->cap_ranges || !c->d_blob.p) {
         c->cap_ranges = grow(c->cap_ranges, nranges, 64);
         const BlobLayout L = blob_layout(c->cap_ranges);
@@ -522,22 +530,24 @@ int ensure_capacity(sieve_ctx *c, uint64_t nranges, uint64_t nchunks, uint64_t n
         if (!c->d_blob.reserve(L.total) || !c->d_counts.reserve(c->cap_ranges) ||
             !c->d_status.reserve(c->cap_ranges))
             return SIEVE_E_NOMEM;
-        if (c->h_blob)
-            (void)hipHostFree(c->h_blob);
-        if (c->h_counts)
-            (void)hipHostFree(c->h_counts);
-        if (c->h_status)
-            (void)hipHostFree(c->h_status);
-        c->h_blob = nullptr;
-        c->h_counts = nullptr;
-        c->h_status = nullptr;
-        if (hipHostMalloc((void **)&c->h_blob, L.total, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void **)&c->h_counts, c->cap_ranges * sizeof(unsigned long long),
-                          hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void **)&c->h_status, c->cap_ranges * sizeof(int32_t), hipHostMallocDefault) !=
-                hipSuccess) {
-            (void)hipGetLastError();
-            return SIEVE_E_NOMEM;
+        for (auto &sl : c->slot) {
+            if (sl.blob)
+                (void)hipHostFree(sl.blob);
+            if (sl.counts)
+                (void)hipHostFree(sl.counts);
+            if (sl.status)
+                (void)hipHostFree(sl.status);
+            sl.blob = nullptr;
+            sl.counts = nullptr;
+            sl.status = nullptr;
+            if (hipHostMalloc((void **)&sl.blob, L.total, hipHostMallocDefault) != hipSuccess ||
+                hipHostMalloc((void **)&sl.counts, c->cap_ranges * sizeof(unsigned long long),
+                              hipHostMallocDefault) != hipSuccess ||
+                hipHostMalloc((void **)&sl.status, c->cap_ranges * sizeof(int32_t), hipHostMallocDefault) !=
+                    hipSuccess) {
+                (void)hipGetLastError();
+                return SIEVE_E_NOMEM;
+            }
         }
         c->h_blob_n = L.total;
         changed = true;
@@ -595,7 +605,10 @@ int ensure_capacity(sieve_ctx *c, uint64_t nranges, uint64_t nchunks, uint64_t n
     if (!c->d_counters.p) {
         if (!c->d_counters.reserve(kNumCounters))
             return SIEVE_E_NOMEM;
-        if (hipHostMalloc((void **)&c->h_flag, 2 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
+        if (hipHostMalloc((void **)&c->slot[0].flag, 2 * sizeof(unsigned long long), hipHostMallocDefault) !=
+                hipSuccess ||
+            hipHostMalloc((void **)&c->slot[1].flag, 2 * sizeof(unsigned long long), hipHostMallocDefault) !=
+                hipSuccess ||
             hipHostMalloc((void **)&c->h_btotal, sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
             return SIEVE_E_NOMEM;
@@ -790,11 +803,39 @@ hipError_t run_phase(sieve_ctx *c, hipStream_t s, int phase, bool use_graph)
     return hipGraphLaunch(c->graph[phase], s);
 }
 
+// Results of a stream-ordered job: a host function on the stream copies
+// them from the job's pinned slot into the caller's arrays.
+struct AsyncResult {
+    sieve_ctx *c;
+    const unsigned long long *counts_src;
+    const int32_t *status_src;
+    const unsigned long long *flag;
+    uint64_t *counts;
+    int32_t *status;
+    uint64_t n;
+};
+
+void deliver_results(void *arg)
+{
+    AsyncResult *r = (AsyncResult *)arg;
+    for (uint64_t i = 0; i < r->n; ++i) {
+        if (r->counts)
+            r->counts[i] = r->counts_src[i];
+        if (r->status)
+            r->status[i] = r->status_src[i];
+    }
+    if (r->flag[0])
+        r->c->last_error = SIEVE_E_DEVICE;  // a kernel refused to run (see its error flag)
+    delete r;
+}
+
 // Runs one job: plan, upload, kernels (graph or direct), results.
-// counts/status (host, n entries) receive per-range results.
+// counts/status (host, n entries) receive per-range results.  With async_ok
+// a job that needs no host decision mid-way (no bucket sieve, no timing)
+// returns once enqueued; its results are written when the stream gets there.
 int run_job_once(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, const uint8_t *mode,
                  const uint64_t *off, const uint64_t *cap, int elem_bytes, void *out, uint64_t *counts,
-                 int32_t *status, hipStream_t stream, bool use_graph, Plan &pl)
+                 int32_t *status, hipStream_t stream, bool use_graph, Plan &pl, bool async_ok)
 {
     int st;
     const uint64_t nlist = pl.nlist;
@@ -804,6 +845,26 @@ int run_job_once(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *h
     if (st != SIEVE_OK)
         return st;
     hipStream_t s = stream ? stream : c->stream;
+    // This job's host slot: the job before last used it; wait until that
+    // job's copies out of it are done.
+    c->cur_slot ^= 1;
+    {
+        sieve_ctx::HostSlot &sl = c->slot[c->cur_slot];
+        if (sl.used && hipEventSynchronize(sl.done) != hipSuccess) {
+            (void)hipGetLastError();
+            return SIEVE_E_DEVICE;
+        }
+        c->h_blob = sl.blob;
+        c->h_counts = sl.counts;
+        c->h_status = sl.status;
+        c->h_flag = sl.flag;
+    }
+    // The scratch is shared: a job on another stream than the last one
+    // waits for it on the device.
+    if (c->last_valid && c->last_stream != s && hipStreamWaitEvent(s, c->last_ev, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return SIEVE_E_DEVICE;
+    }
     const BlobLayout L = blob_layout(c->cap_ranges);
     JobHeader *h = (JobHeader *)c->h_blob;
     memset(h, 0, sizeof *h);
@@ -904,6 +965,46 @@ int run_job_once(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *h
             f = hipStreamSynchronize(s);
         return f;
     };
+    // Marks the end of this job on s: the slot it used and the context's
+    // latest work.
+    auto fence = [&]() -> hipError_t {
+        sieve_ctx::HostSlot &sl = c->slot[c->cur_slot];
+        hipError_t f = hipEventRecord(sl.done, s);
+        if (f == hipSuccess)
+            f = hipEventRecord(c->last_ev, s);
+        if (f == hipSuccess) {
+            sl.used = true;
+            c->last_stream = s;
+            c->last_valid = true;
+        }
+        return f;
+    };
+    if (!buckets && async_ok && !c->timing) {
+        // Stream-ordered: results copied to the slot, then handed to the
+        // caller by a host function on the stream.
+        e = run_phase(c, s, kPhaseWhole, use_graph);
+        if (e == hipSuccess && n)
+            e = hipMemcpyAsync(c->h_counts, c->d_counts.p, n * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess && n)
+            e = hipMemcpyAsync(c->h_status, c->d_status.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->h_flag, c->d_counters.p + kErrorFlag, 2 * sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, s);
+        AsyncResult *r = nullptr;
+        if (e == hipSuccess) {
+            r = new (std::nothrow) AsyncResult{c, c->h_counts, c->h_status, c->h_flag, counts, status, n};
+            if (!r)
+                e = hipErrorOutOfMemory;
+        }
+        if (e == hipSuccess) {
+            e = hipLaunchHostFunc(s, deliver_results, r);
+            if (e != hipSuccess)
+                delete r;
+        }
+        if (e == hipSuccess)
+            e = fence();
+        return e == hipSuccess ? SIEVE_OK : hip_status(e);
+    }
     if (!buckets) {
         e = run_phase(c, s, kPhaseWhole, use_graph);
         if (e == hipSuccess)
@@ -950,6 +1051,8 @@ int run_job_once(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *h
                 e = finish();
         }
     }
+    if (e == hipSuccess)
+        e = fence();
     if (e != hipSuccess)
         return hip_status(e);
     if (c->h_flag[0])
@@ -990,7 +1093,7 @@ int run_job_once(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *h
 // reports SIEVE_E_CAPACITY with its full count.
 int run_job(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, const uint8_t *mode,
             const uint64_t *off, const uint64_t *cap, int elem_bytes, void *out, uint64_t *counts,
-            int32_t *status, hipStream_t stream, bool use_graph)
+            int32_t *status, hipStream_t stream, bool use_graph, bool async_ok = false)
 {
     Plan pl;
     int st = make_plan(c, n, lo, hi, mode, off, cap, elem_bytes, pl);
@@ -998,7 +1101,8 @@ int run_job(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, co
         return st;
     const uint64_t budget = c->bucket_budget;
     if (pl.best <= budget)
-        return run_job_once(c, n, lo, hi, mode, off, cap, elem_bytes, out, counts, status, stream, use_graph, pl);
+        return run_job_once(c, n, lo, hi, mode, off, cap, elem_bytes, out, counts, status, stream, use_graph, pl,
+                            async_ok);
     if (pl.nlist && !out)
         return SIEVE_E_INVAL;
     const uint64_t span = (uint64_t)kValsPerWord * (c->prm.segment_bytes / 8);
@@ -1050,7 +1154,7 @@ int run_job(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, co
         st = make_plan(c, m, glo.data(), ghi.data(), gmode.data(), goff.data(), gcap.data(), elem_bytes, gp);
         if (st == SIEVE_OK)
             st = run_job_once(c, m, glo.data(), ghi.data(), gmode.data(), goff.data(), gcap.data(), elem_bytes,
-                              out, gcnt.data(), gst.data(), stream, use_graph, gp);
+                              out, gcnt.data(), gst.data(), stream, use_graph, gp, false);
         if (st != SIEVE_OK)
             return st;
         for (uint64_t g = 0; g < m; ++g) {
@@ -1145,14 +1249,20 @@ void destroy_ctx(sieve_ctx *c)
     c->d_chunk_off.release();
     c->d_seg_sum.release();
     c->d_seg_base.release();
-    if (c->h_blob)
-        (void)hipHostFree(c->h_blob);
-    if (c->h_counts)
-        (void)hipHostFree(c->h_counts);
-    if (c->h_status)
-        (void)hipHostFree(c->h_status);
-    if (c->h_flag)
-        (void)hipHostFree(c->h_flag);
+    for (auto &sl : c->slot) {
+        if (sl.blob)
+            (void)hipHostFree(sl.blob);
+        if (sl.counts)
+            (void)hipHostFree(sl.counts);
+        if (sl.status)
+            (void)hipHostFree(sl.status);
+        if (sl.flag)
+            (void)hipHostFree(sl.flag);
+        if (sl.done)
+            (void)hipEventDestroy(sl.done);
+    }
+    if (c->last_ev)
+        (void)hipEventDestroy(c->last_ev);
     c->d_tally.release();
     if (c->h_tally)
         (void)hipHostFree(c->h_tally);
@@ -1186,9 +1296,9 @@ void plan_range(uint64_t lo, uint64_t hi, uint32_t pw, uint64_t &ntiles, uint64_
 }
 int run_job(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, const uint8_t *mode,
             const uint64_t *off, const uint64_t *cap, int elem_bytes, void *out, uint64_t *counts, int32_t *status,
-            hipStream_t stream, bool use_graph)
+            hipStream_t stream, bool use_graph, bool async_ok)
 {
-    return ::run_job(c, n, lo, hi, mode, off, cap, elem_bytes, out, counts, status, stream, use_graph);
+    return ::run_job(c, n, lo, hi, mode, off, cap, elem_bytes, out, counts, status, stream, use_graph, async_ok);
 }
 int grow_base_primes(sieve_ctx *c, uint64_t limit) { return ::grow_base_primes(c, limit); }
 }  // namespace rt
@@ -1288,6 +1398,13 @@ int sieve_create(sieve_ctx **out, int device, const sieve_params *p)
             destroy_ctx(c);
             return SIEVE_E_DEVICE;
         }
+    if (hipEventCreateWithFlags(&c->slot[0].done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->slot[1].done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->last_ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        destroy_ctx(c);
+        return SIEVE_E_DEVICE;
+    }
     {
         // This device's copy of the fixed scratch array (the device is
         // current here); host code uses only this address for it.
@@ -1381,8 +1498,13 @@ int sieve_list(sieve_ctx *ctx, uint64_t lo, uint64_t hi, void *out_dev, uint64_t
     int32_t rs = 0;
     // A NULL output with cap 0 only asks for the count.
     void *out = out_dev ? out_dev : (void *)ctx->d_chunk_off.p;
-    int st = run_job(ctx, 1, &lo, &hi, &mode, &off, &cap, elem_bytes, out, n_out, &rs, (hipStream_t)stream,
-                     false);
+    if (stream) {
+        // Stream-ordered: *n_out is written when the stream reaches the end
+        // of the job (a capacity shortfall then shows as *n_out > cap).
+        return set_err(ctx, run_job(ctx, 1, &lo, &hi, &mode, &off, &cap, elem_bytes, out, n_out, nullptr,
+                                    (hipStream_t)stream, false, true));
+    }
+    int st = run_job(ctx, 1, &lo, &hi, &mode, &off, &cap, elem_bytes, out, n_out, &rs, nullptr, false);
     if (st == SIEVE_OK && rs != SIEVE_OK)
         st = rs;
     return set_err(ctx, st);
@@ -1398,7 +1520,7 @@ int sieve_count_batch(sieve_ctx *ctx, const uint64_t *lo, const uint64_t *hi, ui
     if (n == 0)
         return set_err(ctx, SIEVE_OK);
     int st = run_job(ctx, n, lo, hi, nullptr, nullptr, nullptr, 8, nullptr, counts, nullptr,
-                     (hipStream_t)stream, ctx->prm.use_graph != 0);
+                     (hipStream_t)stream, ctx->prm.use_graph != 0, stream != nullptr);
     return set_err(ctx, st);
 }
 
@@ -1420,7 +1542,7 @@ int sieve_list_batch(sieve_ctx *ctx, const uint64_t *lo, const uint64_t *hi, con
     if (n == 0)
         return set_err(ctx, SIEVE_OK);
     int st = run_job(ctx, n, lo, hi, mode, off, cap, elem_bytes, out_dev, counts, status, (hipStream_t)stream,
-                     ctx->prm.use_graph != 0);
+                     ctx->prm.use_graph != 0, stream != nullptr);
     return set_err(ctx, st);
 }
 

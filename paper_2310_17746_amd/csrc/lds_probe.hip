@@ -23,6 +23,9 @@ constexpr int kThreads = 1024;
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 typedef __attribute__((address_space(3))) uint8_t lds_u8;
 
+// Pseudo-random word indices for the random-address patterns: the
+// "lowbias32" integer hash (xorshift-multiply rounds) published by
+// C. Wellons, "Prospecting for Hash Functions" (2018, hash-prospector).
 __host__ __device__ __forceinline__ uint32_t hash32(uint32_t x)
 {
     x ^= x >> 16;

@@ -97,12 +97,33 @@ struct sieve_ctx {
     sieve::rt::DevBuf<unsigned long long> d_chunk_off;
     sieve::rt::DevBuf<unsigned long long> d_seg_sum, d_seg_base;  // chunk-offset scan segments
     sieve::rt::DevBuf<uint32_t> d_gbm, d_garrive;  // split tiles: global planes, arrival counts
-    unsigned char *h_blob = nullptr;  // pinned staging for the blob
+    // Pinned host staging, two slots used in turn by consecutive jobs: the
+    // blob (JobHeader | RangeDesc[] | VisitEntry[]) before its copy to the
+    // device, and the per-range counts, status and the error and overflow
+    // flags after the job.  A slot's event is recorded after its last use on
+    // the stream, so a stream-ordered call can return while its copies are
+    // pending; the job after next waits for it before refilling the slot.
+    struct HostSlot {
+        unsigned char *blob = nullptr;
+        unsigned long long *counts = nullptr;
+        int32_t *status = nullptr;
+        unsigned long long *flag = nullptr;
+        hipEvent_t done = nullptr;
+        bool used = false;
+    };
+    HostSlot slot[2];
+    int cur_slot = 0;
+    unsigned char *h_blob = nullptr;         // the current job's slot buffers
+    unsigned long long *h_counts = nullptr;
+    int32_t *h_status = nullptr;
+    unsigned long long *h_flag = nullptr;
     size_t h_blob_n = 0;
-    unsigned long long *h_counts = nullptr;  // pinned
-    int32_t *h_status = nullptr;             // pinned
-    unsigned long long *h_flag = nullptr;    // pinned copy of the error and overflow flags
     uint64_t cap_ranges = 0, cap_chunks = 0;
+    // End of the context's latest job on the stream it ran on; a job on
+    // another stream waits for it first (the scratch is shared).
+    hipEvent_t last_ev = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool last_valid = false;
 
     // Bucket sieve scratch: per-tile counts, cursors and offsets; entries.
     sieve::rt::DevBuf<uint32_t> d_bcount, d_bcursor, d_bdata;
@@ -155,11 +176,14 @@ int hip_status(hipError_t e);
 uint64_t isqrt_host(uint64_t n);
 // Tile plan of [lo, hi) for pw plane words per tile.
 void plan_range(uint64_t lo, uint64_t hi, uint32_t pw, uint64_t &ntiles, uint64_t &base, uint32_t &last_words);
-// One job over n ranges (see api.hip); synchronous on `stream` (NULL: the
-// context stream).  counts/status are host arrays of n entries (may be NULL).
+// One job over n ranges (see api.hip) on `stream` (NULL: the context stream).
+// counts/status are host arrays of n entries (may be NULL).  Synchronous
+// unless async_ok: then a job that needs no host decision mid-way returns
+// once enqueued, and counts/status are written when the stream reaches its
+// end.
 int run_job(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, const uint8_t *mode,
             const uint64_t *off, const uint64_t *cap, int elem_bytes, void *out, uint64_t *counts, int32_t *status,
-            hipStream_t stream, bool use_graph);
+            hipStream_t stream, bool use_graph, bool async_ok = false);
 // Makes the resident base primes cover `limit`.
 int grow_base_primes(sieve_ctx *c, uint64_t limit);
 
