@@ -14,7 +14,7 @@ its algorithmic LDS traffic (4 bytes per mark, read-modify-write of one
 bytes read back by the popcount) over its average duration, measured with
 HIP events on the stream it runs on, against the nominal LDS bandwidth
 derived from the unit counts (128 B/clk/CU * 256 CUs * 2.4 GHz).  The mark
-count is exact: for every base prime p > 61 the number of m coprime to 30
+count is exact: for every base prime p > 73 the number of m coprime to 30
 with max(p^2, range base) <= m*p < range-span end.  Beside it: the measured
 rate of the instruction itself (LDS probe, this run) and, from the committed
 counter summary of the same kernel sources and launch shape, the LDS bytes
@@ -85,7 +85,7 @@ def coprime30_upto(n: np.ndarray) -> np.ndarray:
 def lds_work(lo: int, hi: int, segment_bytes: int) -> tuple[int, int]:
     """(marks, plane words) the sieve kernel performs on [lo, hi).
 
-    Primes 5..61 are presieved; every other base prime p marks p*m for the
+    Primes 5..73 are presieved; every other base prime p marks p*m for the
     cofactors m coprime to 30 (multiples of 2, 3 are outside the wheel and
     multiples of 5 are already cleared by the presieve)."""
     base = lo - lo % 6
@@ -93,7 +93,7 @@ def lds_work(lo: int, hi: int, segment_bytes: int) -> tuple[int, int]:
     words = (n1 + 31) // 32
     end = base + 192 * words
     p = small_primes(math.isqrt(hi - 1))
-    p = p[p > 61]                                  # 5..61 are presieved by patterns
+    p = p[p > 73]                                  # 5..73 are presieved by patterns
     # per tile the start is max(p^2, tile base); the sum over the tiles is the
     # sum over the whole span with the p^2 clamp, since tiles are contiguous
     # (the tile size only sets where they meet: segment_bytes does not change

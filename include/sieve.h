@@ -81,8 +81,8 @@ typedef struct sieve_ctx sieve_ctx;
  *                    covers 24 * segment_bytes consecutive integers.
  *   block_threads    threads per workgroup: 256, 512 or 1024 (default 1024).
  *   presieve_groups  number of repeating-pattern groups used to initialise
- *                    the planes (0..5; 5 covers every prime 5..61).  0 means
- *                    default; SIEVE_PRESIEVE_NONE disables the presieve.
+ *                    the planes (0..6; 6 covers every prime 5..73).  0 means
+ *                    default (6); SIEVE_PRESIEVE_NONE disables the presieve.
  *   split_hits       target hits per marking work item (default 64): primes
  *                    with more hits per tile are split over several lanes.
  *   bucket_threshold primes at least this large go through the bucket
@@ -102,11 +102,15 @@ typedef struct sieve_ctx sieve_ctx;
  *                    exercises the overflow re-run (tests).
  *   cofactor_skip    where marks whose cofactor is a multiple of 5 are
  *                    skipped (such values are already cleared by the 5 of the
- *                    presieve): 0 (default) or SIEVE_SKIP_SPLIT in the
- *                    bucket sieve and for the primes whose tile work is
- *                    split over several lanes (the small ones, many hits);
- *                    SIEVE_SKIP_ALL in the whole per-tile marking loop too;
- *                    SIEVE_SKIP_NONE nowhere.  Needs presieve_groups >= 1.
+ *                    presieve): SIEVE_SKIP_SPLIT in the bucket sieve and for
+ *                    the primes whose tile work is split over several lanes
+ *                    (the small ones, many hits), except the fixed-mask
+ *                    ones; 0 (default) the same, plus the fixed-mask items
+ *                    when the shape runs four waves per SIMD (one 1024- or
+ *                    two 512-thread workgroups per CU); SIEVE_SKIP_ALL in
+ *                    every per-tile marking loop but the carried-register
+ *                    one; SIEVE_SKIP_NONE nowhere.  Needs presieve_groups
+ *                    >= 1.
  *   dense_hits       primes with at least this many hits per plane per tile
  *                    (default 512) are split over a multiple of 32 lanes, so
  *                    that each lane's hits share one bit position and need

@@ -39,9 +39,10 @@ using sieve::rt::DevBuf;
 
 namespace {
 
-// Presieve groups: consecutive primes whose product stays below 2^18 bits.
+// Presieve groups: consecutive primes, each group's period (their product)
+// below 2^19 bits.
 const uint32_t kGroupPrimes[kMaxGroups][4] = {
-    {5, 7, 11, 13}, {17, 19, 23, 0}, {29, 31, 37, 0}, {41, 43, 47, 0}, {53, 59, 61, 0}};
+    {5, 7, 11, 13}, {17, 19, 23, 0}, {29, 31, 37, 0}, {41, 43, 47, 0}, {53, 59, 61, 0}, {67, 71, 73, 0}};
 
 constexpr uint32_t kFinalizeGrid = 256;
 
@@ -264,6 +265,8 @@ int install_primes(sieve_ctx *c, uint64_t limit)
         if (c->prm.dense_hits != SIEVE_DENSE_NEVER && hits >= c->prm.dense_hits && kd == ks) {
             g = 32 * std::max<uint64_t>(1, hits / (32ull * c->prm.split_hits));
             g = std::min<uint64_t>(g, 0xFFE0);
+            if (g % 5 == 0)
+                g -= 32;  // a lane's cofactors then run through every residue mod 5
             kd = ks + 1;
         } else {
             g = plane_bits / ((uint64_t)P[ks] * c->prm.split_hits);
@@ -620,6 +623,24 @@ int ensure_capacity(sieve_ctx *c, uint64_t nranges, uint64_t nchunks, uint64_t n
     return SIEVE_OK;
 }
 
+// Where the sieve kernel skips marks whose cofactor is a multiple of 5 (the
+// presieve has cleared them): SieveArgs::skip5.  By default the split items
+// skip them, and the fixed-mask (dense) items too in the launch shapes of
+// four waves per SIMD, whose time goes to LDS operations; the shape of six
+// waves per SIMD is bound by VALU issue, where the skip's setup costs more
+// than the ORs it saves.
+uint32_t skip5_mode(const sieve_ctx *c)
+{
+    if (c->ngroups < 1 || c->prm.cofactor_skip == SIEVE_SKIP_NONE)
+        return 0;
+    if (c->prm.cofactor_skip == SIEVE_SKIP_ALL)
+        return 1;
+    if (c->prm.cofactor_skip == SIEVE_SKIP_SPLIT)
+        return 2;
+    const bool six = c->prm.block_threads < 1024 && (c->prm.block_threads / 64) * c->prm.wg_per_cu >= 24;
+    return six ? 2u : 3u;
+}
+
 enum Phase { kPhaseWhole = 0, kPhaseBucketCount = 1, kPhaseRest = 2, kPhaseDirect = 3 };
 
 // Enqueues one phase of the job kernels on stream s; also used under graph
@@ -711,8 +732,7 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed, boo
     a.restore1 = c->restore1;
     a.restore5 = c->restore5;
     a.pw = pw;
-    a.skip5 = c->ngroups < 1 || c->prm.cofactor_skip == SIEVE_SKIP_NONE ? 0u
-              : c->prm.cofactor_skip == SIEVE_SKIP_ALL ? 1u : 2u;
+    a.skip5 = skip5_mode(c);
     a.bitmap = c->d_bitmap.p;
     a.chunk_counts = c->d_chunk_counts.p;
     a.bdata = c->d_bdata.p;
@@ -1650,8 +1670,7 @@ int sieve_count_batch_static(sieve_ctx *ctx, const uint64_t *lo, const uint64_t 
         a.restore1 = ctx->restore1;
         a.restore5 = ctx->restore5;
         a.pw = pw;
-        a.skip5 = ctx->ngroups < 1 || ctx->prm.cofactor_skip == SIEVE_SKIP_NONE ? 0u
-                  : ctx->prm.cofactor_skip == SIEVE_SKIP_ALL ? 1u : 2u;
+        a.skip5 = skip5_mode(ctx);
         const bool u24 = top < 2 || isqrt_host(top - 1) < (1u << 24) - 8;
         e = launch_sieve(a, ctx->prm.block_threads, ctx->prm.wg_per_cu, (uint32_t)ctx->cus * ctx->prm.wg_per_cu,
                          u24, s);

@@ -194,6 +194,49 @@ __device__ __forceinline__ void mark_plane_fixed(uint32_t start, uint32_t step, 
         lds_or(a, mask, t);
 }
 
+// As mark_plane_fixed, skipping hit n when n = s (mod 5): the lane's hits
+// n = 0, 1, 2, ... have cofactors running through the residues mod 5 with
+// period 5 (its step is g P bits with g prime to 5), and the skipped ones are
+// multiples of 5, already cleared by the presieve.  Four ORs per period of
+// five hits, at byte offsets fixed for the lane.  s in 0..4.
+__device__ __forceinline__ void mark_plane_fixed_skip5(uint32_t start, uint32_t step, uint32_t nbits, uint32_t s,
+                                                       MarkTally &t)
+{
+    if (start >= nbits)
+        return;
+    {
+        const uint64_t h = t.run(start, step, nbits);
+        t.skip(h > s ? (h - s - 1) / 5 + 1 : 0);
+    }
+    const uint32_t mask = 1u << (start & 31);
+    const uint32_t end = nbits >> 3;  // nbits is a whole number of words
+    const uint32_t sb = step >> 3;
+    uint32_t a = (start >> 3) & ~3u;
+    if (sb < end / 5) {
+        const uint32_t s2 = sb + sb, s3 = s2 + sb, s4 = s3 + sb, s5 = s4 + sb;
+        const uint32_t o0 = s == 0 ? sb : 0u;
+        const uint32_t o1 = s <= 1 ? s2 : sb;
+        const uint32_t o2 = s <= 2 ? s3 : s2;
+        const uint32_t o3 = s <= 3 ? s4 : s3;
+        const uint32_t lim = end - 4 * sb;  // a < lim keeps a + 4*sb < end
+        while (a < lim) {
+            asm volatile("" : "+v"(a));
+            lds_or(a + o0, mask, t);
+            lds_or(a + o1, mask, t);
+            lds_or(a + o2, mask, t);
+            lds_or(a + o3, mask, t);
+            a += s5;
+        }
+    }
+    for (uint32_t n = 0; n < 5; ++n) {
+        const uint32_t x = a + n * sb;
+        if (x >= end)
+            break;
+        if (n != s)
+            lds_or(x, mask, t);
+    }
+}
+
 // As mark_plane, for a lane whose hits n = 0, 1, 2, ... have cofactors
 // running through the residues mod 5 with period 5, skipping hit n when
 // n = s (mod 5): those values are multiples of 5, already cleared by the
@@ -526,11 +569,21 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W))) k_
                                 tally.check(B, id1t + off, 1, pc.p);
                             if (id5t + off < nbits)
                                 tally.check(B, id5t + off, 5, pc.p);
-                            if (v < n_dense) {
+                            if (v < n_dense && a.skip5 != 1 && a.skip5 != 3) {
                                 // g is a multiple of 32: fixed-mask marking
                                 mark_plane_fixed(id1t + off, step, nbits, tally);
                                 mark_plane_fixed(id5t + off + off5, step, nbits + off5, tally);
-                            } else if (a.skip5 == 1 || (a.skip5 == 2 && v < n_items)) {
+                            } else if (v < n_dense) {
+                                // fixed-mask marking without the multiples of 5
+                                // (g is a multiple of 32 and prime to 5)
+                                const uint32_t inv5 = pc.r >> 29;
+                                const uint32_t ginv = inv_mod5(g);
+                                const uint32_t c1 = (cofactor_mod5(b5, id1t, 1, inv5) + j) % 5u;
+                                const uint32_t c5 = (cofactor_mod5(b5, id5t, 0, inv5) + j) % 5u;
+                                mark_plane_fixed_skip5(id1t + off, step, nbits, ((5u - c1) * ginv) % 5u, tally);
+                                mark_plane_fixed_skip5(id5t + off + off5, step, nbits + off5, ((5u - c5) * ginv) % 5u,
+                                                       tally);
+                            } else if (a.skip5 == 1 || (a.skip5 >= 2 && v < n_items)) {
                                 // hit n of this lane has cofactor m0 + 6(j + n g) = c + n g (mod 5);
                                 // it is a multiple of 5 when n = -c / g (mod 5)
                                 const uint32_t inv5 = pc.r >> 29;
@@ -724,9 +777,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W))) k_
                     uint32_t c1 = pl1[w], c5 = pl5[w];
                     pl1[w] = 0;
                     pl5[w] = 0;
-                    if (w == 0 && B < 62) {
-                        // The presieved primes themselves (5..61) lie in word 0
-                        // of any tile based below 62: the patterns marked them.
+                    if (w == 0 && B < 74) {
+                        // The presieved primes themselves (5..73) lie in word 0
+                        // of any tile based below 74: the patterns marked them.
                         c1 &= ~(a.restore1 >> (B / 6));
                         c5 &= ~(a.restore5 >> (B / 6));
                     }

@@ -25,7 +25,7 @@ namespace sieve {
 constexpr uint32_t kChunkWords = 512;                       // u64 bitmap words per chunk
 constexpr uint64_t kValsPerWord = 192;                      // integers per plane word
 constexpr uint64_t kChunkVals = kValsPerWord * kChunkWords;  // integers per chunk
-constexpr int kMaxGroups = 5;                               // presieve pattern groups
+constexpr int kMaxGroups = 6;                               // presieve pattern groups
 constexpr uint32_t kCompactThreads = 512;                   // one bitmap word per thread
 constexpr uint32_t kStagePerWave = 512;                     // compaction staging entries per wave
 constexpr uint32_t kFinalizeThreads = 1024;
@@ -134,7 +134,8 @@ struct SieveArgs {
     uint32_t ngroups;
     uint32_t restore1, restore5;  // bits of the presieved primes in word 0 of a tile based at 0
     uint32_t pw;                  // plane words per tile
-    uint32_t skip5;               // marks with 5 | cofactor skipped (5 is presieved): 1 every item, 2 split items
+    uint32_t skip5;               // marks with 5 | cofactor skipped (5 is presieved): 0 none, 1 every item,
+                                  // 2 split items, 3 split and fixed-mask (dense) items
     unsigned long long *bitmap;   // list scratch (u64 words)
     uint32_t *chunk_counts;       // per chunk prime count
     const uint32_t *bdata;        // bucket entries: bit | plane << 31

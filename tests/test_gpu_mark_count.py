@@ -3,7 +3,7 @@
 
 Over a range [lo, hi) the tiles cover the wheel values of [B, E), with
 B = lo - lo mod 6 and E = B + 192 * ceil(n / 32) for n = ceil((hi - B - 1) / 6)
-indices per plane.  Every base prime P above the presieved ones (5..61) with
+indices per plane.  Every base prime P above the presieved ones (5..73) with
 P * P < hi must visit exactly the multiples m * P with gcd(m, 6) = 1 and
 max(P * P, B) <= m * P < E (Sec. 1.1: marking starts at the square;
 Sec. 2.1: the arrays hold only values coprime to 6), whichever path marks it:
@@ -30,7 +30,7 @@ torch = pytest.importorskip("torch")
 pkg = pytest.importorskip("paper_2310_17746_amd")
 
 LIB = os.path.join(os.path.dirname(pkg.__file__), "libsieve_markcount.so")
-PRESIEVED_MAX = 61
+PRESIEVED_MAX = 73  # the default presieve groups cover the primes 5..73
 
 
 @pytest.fixture(scope="module")

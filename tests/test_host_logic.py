@@ -169,7 +169,7 @@ def test_first_mismatch_helper():
 
 def test_bench_mark_count_against_brute_force():
     # the roofline's algorithmic LDS work: multiples p*m of every base prime
-    # p > 61 from max(p^2, base) to the end of the last plane word, with m
+    # p > 73 from max(p^2, base) to the end of the last plane word, with m
     # coprime to 30 (2 and 3 are off the wheel, 5 is presieved)
     import bench
     rng = random.Random(12)
@@ -180,7 +180,7 @@ def test_bench_mark_count_against_brute_force():
         base = lo - lo % 6
         end = base + 192 * words
         want = 0
-        for p in range(67, math.isqrt(hi - 1) + 1):
+        for p in range(79, math.isqrt(hi - 1) + 1):
             if all(p % q for q in range(2, math.isqrt(p) + 1)):
                 for v in range(max(p * p, base), end):
                     if v % p == 0 and math.gcd(v // p, 30) == 1:
