@@ -10,6 +10,9 @@ Contents
   ``oracle.c`` (Fig. 1 of the paper, segmented as in Sec. 2.2, each prime
   starting at its square as in Sec. 1.1 and Sec. 2.4), one byte per integer,
   no wheel.  Loaded through ctypes from ``liboracle.so`` (built by ``build``).
+* ``count_wide`` / ``primes_wide``: the same definition for values past 2^64
+  (unsigned 128-bit arithmetic in ``oracle.c``; base primes listed by the
+  64-bit sieve), for windows of the paper's next step beyond 64 bits (Sec. 6).
 * ``brute``: trial division and deterministic Miller-Rabin, for pins.
 * ``wheel``: the 6k+1/6k+5 index mapping (Sec. 2.1, Fig. 2) and the start
   index of Table 1 (Sec. 3), both as the paper states them and as their plain
@@ -59,6 +62,8 @@ def _load():
                                     ctypes.c_uint64, ctypes.c_int, ctypes.c_int]
         lib.oracle_simple_primes.restype = ctypes.c_int64
         lib.oracle_simple_primes.argtypes = [ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint64]
+        lib.oracle_wide.restype = ctypes.c_int64
+        lib.oracle_wide.argtypes = [ctypes.c_uint64] * 4 + [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -109,4 +114,32 @@ def simple_primes(limit: int) -> np.ndarray:
         raise ValueError("oracle_simple_primes(%d) failed" % limit)
     out = np.empty(max(n, 1), dtype=np.uint32)
     lib.oracle_simple_primes(limit, out.ctypes.data, n)
+    return out[:n]
+
+
+def _halves(x: int):
+    return x & (2 ** 64 - 1), x >> 64
+
+
+def count_wide(lo: int, hi: int, threads: int | None = None) -> int:
+    """Number of primes in [lo, hi) for values up to 2^128 (hi - lo < 2^63,
+    isqrt(hi - 1) < 2^40)."""
+    if threads is None:
+        threads = default_threads()
+    r = _load().oracle_wide(*_halves(lo), *_halves(hi), None, 0, threads)
+    if r < 0:
+        raise ValueError("oracle_wide(%d, %d) failed with %d" % (lo, hi, r))
+    return int(r)
+
+
+def primes_wide(lo: int, hi: int, threads: int | None = None) -> np.ndarray:
+    """Primes of [lo, hi) beyond 64 bits, as an (n, 2) uint64 array of
+    (low half, high half) per prime, in increasing order."""
+    if threads is None:
+        threads = default_threads()
+    n = count_wide(lo, hi, threads)
+    out = np.empty((max(n, 1), 2), dtype=np.uint64)
+    r = _load().oracle_wide(*_halves(lo), *_halves(hi), out.ctypes.data, n, threads)
+    if r != n:
+        raise ValueError("oracle_wide list of [%d, %d) returned %d, expected %d" % (lo, hi, r, n))
     return out[:n]

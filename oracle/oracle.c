@@ -278,3 +278,195 @@ int64_t oracle_simple_primes(uint64_t limit, uint32_t *out, uint64_t cap)
     free(p);
     return n;
 }
+
+/* ------------------------------------------------------------------------
+ * Ranges beyond 64 bits (the paper's next step, Sec. 6: numbers past the
+ * 64-bit integers).  The same plain definition, with values held as
+ * unsigned __int128: base primes are all primes <= isqrt(hi - 1) (listed by
+ * the 64-bit sieve above, which needs isqrt(hi - 1) < 2^40), and every
+ * window of ORACLE_WINDOW integers clears the multiples of each base prime p
+ * from max(p*p, first multiple >= window start) on.  Values are passed and
+ * returned as pairs of uint64 (low half first).
+ * ------------------------------------------------------------------------ */
+typedef unsigned __int128 u128;
+
+static u128 make128(uint64_t lo, uint64_t hi) { return ((u128)hi << 64) | lo; }
+
+/* floor(sqrt(n)) by Newton's iteration on 128-bit integers. */
+static u128 isqrt128(u128 n)
+{
+    if (n < 2)
+        return n;
+    int bits = 0;
+    for (u128 t = n; t; t >>= 1)
+        ++bits;
+    u128 x = (u128)1 << ((bits + 1) / 2); /* x >= sqrt(n) */
+    for (;;) {
+        u128 y = (x + n / x) >> 1;
+        if (y >= x)
+            break;
+        x = y;
+    }
+    while (x > n / x)
+        --x;
+    while (x + 1 <= n / (x + 1))
+        ++x;
+    return x;
+}
+
+/* The base primes of the last call, kept for the next one with the same
+   bound (listing them is most of a small window's cost). */
+static pthread_mutex_t wide_lock = PTHREAD_MUTEX_INITIALIZER;
+static uint64_t *wide_primes = NULL;
+static uint64_t wide_np = 0, wide_bound = 0;
+
+struct wjob {
+    u128 lo, hi;
+    const uint64_t *primes;
+    uint64_t np, nwin, next;
+    pthread_mutex_t lock;
+    uint64_t *win_count;
+    uint64_t **win_list; /* list mode: pairs (lo half, hi half) */
+    int list, failed;
+};
+
+static void *wide_worker(void *arg)
+{
+    struct wjob *jb = (struct wjob *)arg;
+    uint8_t *buf = (uint8_t *)malloc(ORACLE_WINDOW);
+    for (;;) {
+        pthread_mutex_lock(&jb->lock);
+        uint64_t i = jb->next++;
+        int stop = jb->failed || !buf;
+        if (!buf)
+            jb->failed = 1;
+        pthread_mutex_unlock(&jb->lock);
+        if (i >= jb->nwin || stop)
+            break;
+        u128 w = jb->lo + (u128)i * ORACLE_WINDOW;
+        u128 we = jb->hi - w < ORACLE_WINDOW ? jb->hi : w + ORACLE_WINDOW;
+        uint64_t len = (uint64_t)(we - w);
+        memset(buf, 1, len);
+        for (uint64_t k = 0; k < jb->np; ++k) {
+            u128 p = jb->primes[k];
+            u128 s = p * p;
+            if (s >= we)
+                break;
+            if (s < w)
+                s = w + (p - w % p) % p; /* first multiple of p >= w */
+            for (u128 j = s; j < we; j += p)
+                buf[(uint64_t)(j - w)] = 0;
+        }
+        for (uint64_t j = 0; j < len && w + j < 2; ++j)
+            buf[j] = 0;
+        uint64_t c = 0;
+        for (uint64_t j = 0; j < len; ++j)
+            c += buf[j];
+        jb->win_count[i] = c;
+        if (jb->list) {
+            uint64_t *l = (uint64_t *)malloc((size_t)((c ? c : 1) * 2 * sizeof(uint64_t)));
+            if (!l) {
+                pthread_mutex_lock(&jb->lock);
+                jb->failed = 1;
+                pthread_mutex_unlock(&jb->lock);
+                break;
+            }
+            uint64_t q = 0;
+            for (uint64_t j = 0; j < len; ++j) {
+                if (!buf[j])
+                    continue;
+                u128 v = w + j;
+                l[q++] = (uint64_t)v;
+                l[q++] = (uint64_t)(v >> 64);
+            }
+            jb->win_list[i] = l;
+        }
+    }
+    free(buf);
+    return NULL;
+}
+
+/* Number of primes in [lo, hi) (or, with out, their list as uint64 pairs,
+   written when the count fits in cap).  hi - lo < 2^63, isqrt(hi - 1) < 2^40.
+   Negative on invalid input or allocation failure. */
+int64_t oracle_wide(uint64_t lo_lo, uint64_t lo_hi, uint64_t hi_lo, uint64_t hi_hi, uint64_t *out, uint64_t cap,
+                    int nthreads)
+{
+    const u128 lo = make128(lo_lo, lo_hi), hi = make128(hi_lo, hi_hi);
+    if (lo > hi || hi - lo >= ((u128)1 << 63))
+        return -1;
+    if (lo == hi)
+        return 0;
+    const u128 L = hi > 1 ? isqrt128(hi - 1) : 0;
+    if (L >= ((u128)1 << 40))
+        return -1;
+    if (nthreads < 1)
+        nthreads = 1;
+
+    pthread_mutex_lock(&wide_lock);
+    if (!wide_primes || wide_bound != (uint64_t)L) {
+        free(wide_primes);
+        wide_primes = NULL;
+        wide_np = 0;
+        int64_t n = oracle_count(0, (uint64_t)L + 1, nthreads);
+        uint64_t *p = n >= 0 ? (uint64_t *)malloc((size_t)((n ? n : 1) * sizeof(uint64_t))) : NULL;
+        if (!p || oracle_list(0, (uint64_t)L + 1, p, (uint64_t)n, 8, nthreads) != n) {
+            free(p);
+            pthread_mutex_unlock(&wide_lock);
+            return -2;
+        }
+        wide_primes = p;
+        wide_np = (uint64_t)n;
+        wide_bound = (uint64_t)L;
+    }
+
+    struct wjob jb;
+    memset(&jb, 0, sizeof jb);
+    jb.lo = lo;
+    jb.hi = hi;
+    jb.primes = wide_primes;
+    jb.np = wide_np;
+    jb.list = out != NULL;
+    jb.nwin = (uint64_t)((hi - lo + ORACLE_WINDOW - 1) / ORACLE_WINDOW);
+    jb.win_count = (uint64_t *)calloc(jb.nwin, sizeof(uint64_t));
+    jb.win_list = jb.list ? (uint64_t **)calloc(jb.nwin, sizeof(uint64_t *)) : NULL;
+    if (!jb.win_count || (jb.list && !jb.win_list)) {
+        free(jb.win_count);
+        free(jb.win_list);
+        pthread_mutex_unlock(&wide_lock);
+        return -2;
+    }
+    pthread_mutex_init(&jb.lock, NULL);
+    if ((uint64_t)nthreads > jb.nwin)
+        nthreads = (int)jb.nwin;
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
+    int started = 0;
+    for (int t = 0; th && t < nthreads; ++t)
+        if (pthread_create(&th[t], NULL, wide_worker, &jb) == 0)
+            ++started;
+    if (started == 0)
+        wide_worker(&jb);
+    for (int t = 0; t < started; ++t)
+        pthread_join(th[t], NULL);
+    free(th);
+
+    int64_t total = jb.failed ? -2 : 0;
+    if (!jb.failed)
+        for (uint64_t i = 0; i < jb.nwin; ++i)
+            total += (int64_t)jb.win_count[i];
+    if (jb.list && total >= 0 && (uint64_t)total <= cap) {
+        uint64_t off = 0;
+        for (uint64_t i = 0; i < jb.nwin; ++i) {
+            memcpy(out + 2 * off, jb.win_list[i], (size_t)(jb.win_count[i] * 2 * sizeof(uint64_t)));
+            off += jb.win_count[i];
+        }
+    }
+    if (jb.win_list)
+        for (uint64_t i = 0; i < jb.nwin; ++i)
+            free(jb.win_list[i]);
+    free(jb.win_list);
+    free(jb.win_count);
+    pthread_mutex_destroy(&jb.lock);
+    pthread_mutex_unlock(&wide_lock);
+    return total;
+}

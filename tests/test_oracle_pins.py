@@ -212,3 +212,25 @@ def test_mark_count_closed_form():
         for v in range(P * P, 3000, P):
             if math.gcd(v // P, 6) == 1:
                 assert v % 6 in (1, 5)
+
+
+def test_wide_oracle_matches_64bit_oracle_and_brute_force():
+    # the 128-bit arithmetic where the 64-bit oracle also applies
+    for lo, hi in [(0, 400), (2 ** 50 - 5000, 2 ** 50 + 10 ** 5), (10 ** 12 - 77, 10 ** 12 + 30011)]:
+        got = oracle.primes_wide(lo, hi)
+        assert np.all(got[:, 1] == 0)
+        assert np.array_equal(got[:, 0], oracle.primes(lo, hi, elem_bytes=8))
+        assert oracle.count_wide(lo, hi) == len(got)
+    assert [int(x) for x in oracle.primes_wide(0, 60)[:, 0]] == brute.primes_td(0, 60)
+
+
+def test_wide_oracle_beyond_64_bits_against_miller_rabin():
+    # every wheel candidate of a window just above 2^64 (Miller-Rabin with the
+    # first twelve prime bases is exact there, far below 3.18e23)
+    lo, hi = 2 ** 64 + 1, 2 ** 64 + 3001
+    got = oracle.primes_wide(lo, hi)
+    vals = [int(a) | (int(b) << 64) for a, b in got]
+    assert vals == sorted(set(vals)) and all(lo <= v < hi for v in vals)
+    want = [v for v in range(lo, hi) if v % 6 in (1, 5) and brute.is_prime_mr(v)]
+    assert vals == want
+    assert len(vals) > 50
