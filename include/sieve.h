@@ -269,6 +269,61 @@ int sieve_count_batch_static(sieve_ctx *ctx, const uint64_t *lo, const uint64_t 
                              uint64_t *counts, void *stream);
 
 /*
+ * Windows beyond the 64-bit calls' domain.  Sec. 6 names ranges past 2^64 as
+ * the step after this method; these calls take the same wheel sieve there.
+ * A value is a sieve_u128 (lo = bits 0..63, hi = bits 64..127).  A window
+ * [lo, hi) must satisfy 2^40 <= lo <= hi and hi - lo <= SIEVE_WIDE_MAX_SPAN,
+ * else SIEVE_E_INVAL (ranges below 2^40 belong to the 64-bit calls).  The
+ * window is sieved in offsets from its base W = lo - lo mod 6: bit i of
+ * plane A_r stands for W + 6i + r (Sec. 2.1 with the segment base W), each
+ * base prime P starts from (W - 1) mod P through Table 1 (Sec. 3) or at P*P
+ * when that lies past W (Sec. 2.4), and the survivors are counted or listed
+ * as W + offset.  Base primes: every prime below 2^32 resident plus an
+ * extension list of 64-bit primes from 2^32 up to the extension limit; a
+ * window needs isqrt(hi - 1) within them, else SIEVE_E_RANGE.  These calls
+ * wait for the context's earlier stream-ordered jobs, run on `stream` (NULL:
+ * the context stream) and return when done.
+ */
+typedef struct sieve_u128 {
+    uint64_t lo, hi;
+} sieve_u128;
+
+#define SIEVE_WIDE_MIN_LO ((uint64_t)1 << 40)
+#define SIEVE_WIDE_MAX_SPAN ((uint64_t)1 << 40)
+#define SIEVE_WIDE_MAX_BASE ((uint64_t)1 << 36)
+
+/*
+ * Makes the base primes cover `limit` <= SIEVE_WIDE_MAX_BASE (else
+ * SIEVE_E_INVAL): below 2^32 this is sieve_base_primes(limit); above, every
+ * prime below 2^32 becomes resident and the primes in [2^32, limit] are
+ * produced by this library's own 64-bit list path into the extension list
+ * (8 bytes each on the device).  A smaller limit than the current one does
+ * nothing.  *n_out (optional) receives resident plus extension primes.
+ */
+int sieve_base_primes_wide(sieve_ctx *ctx, uint64_t limit, uint64_t *n_out);
+
+/* Current extension limit (0 when there is no extension list). */
+int sieve_ext_limit(const sieve_ctx *ctx, uint64_t *limit);
+
+/*
+ * Number of primes in the window [*lo, *hi) into *count (host); lo, hi and
+ * count are host pointers.
+ */
+int sieve_count_wide(sieve_ctx *ctx, const sieve_u128 *lo, const sieve_u128 *hi, uint64_t *count,
+                     void *stream);
+
+/*
+ * Writes the primes of the window [*lo, *hi) in strictly increasing order
+ * to out_dev (device memory owned by the caller, cap 16-byte elements, each
+ * a sieve_u128); *n_out (host, required) receives the count.  If the count
+ * exceeds cap nothing is guaranteed to be written, *n_out holds the required
+ * count and the call returns SIEVE_E_CAPACITY.  out_dev may be NULL with
+ * cap 0 to ask for the count only.
+ */
+int sieve_list_wide(sieve_ctx *ctx, const sieve_u128 *lo, const sieve_u128 *hi, sieve_u128 *out_dev,
+                    uint64_t cap, uint64_t *n_out, void *stream);
+
+/*
  * A rigorous upper bound on the number of primes in [lo, hi), used for
  * output sizing and admission: the minimum of (values coprime to 6 in the
  * range + 2) and the Brun-Titchmarsh bound 2y/ln y (y = hi - lo > 1) of

@@ -19,9 +19,10 @@ import os
 
 import numpy as np
 
-__all__ = ["Sieve", "Server", "Generator", "SieveError", "Params", "ListResult", "list_bound", "wheel_start", "plan_range", "probe_lds",
+__all__ = ["Sieve", "Server", "Generator", "SieveError", "Params", "ListResult", "U128", "list_bound",
+           "list_bound_wide", "wide_values", "wheel_start", "plan_range", "probe_lds",
            "lib_path", "load_library", "SIEVE_OK", "SIEVE_E_CAPACITY", "SIEVE_E_LIMIT",
-           "STATIC_MAX_RANGES"]
+           "STATIC_MAX_RANGES", "WIDE_MIN_LO", "WIDE_MAX_SPAN", "WIDE_MAX_BASE"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libsieve.so")
@@ -39,6 +40,9 @@ SIEVE_E_CANCELLED = -8
 SIEVE_E_IO = -9
 SIEVE_E_LIMIT = -10
 STATIC_MAX_RANGES = 1024        # ranges per sieve_count_batch_static call
+WIDE_MIN_LO = 1 << 40            # windows of the wide calls start here or later
+WIDE_MAX_SPAN = 1 << 40          # and span at most this many integers
+WIDE_MAX_BASE = 1 << 36          # largest base-prime limit of the wide calls
 PRESIEVE_NONE = 0xFFFFFFFF
 BUCKET_NEVER = 0xFFFFFFFF
 BUCKET_EXACT = 1
@@ -65,6 +69,17 @@ class Params(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class U128(ctypes.Structure):
+    """sieve_u128: a 128-bit value as two 64-bit halves."""
+    _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_uint64)]
+
+    @classmethod
+    def of(cls, v: int) -> "U128":
+        if not 0 <= v < 1 << 128:
+            raise ValueError("value outside [0, 2^128)")
+        return cls(v & (2 ** 64 - 1), v >> 64)
 
 
 class ServerParams(ctypes.Structure):
@@ -128,6 +143,12 @@ def load_library():
         "sieve_list_batch": (ctypes.c_int, [_p, _p, _p, _p, _u64, _p, _p, _p, ctypes.c_int,
                                             _p, _p, _p]),
         "sieve_list_bound": (_u64, [_u64, _u64]),
+        "sieve_base_primes_wide": (ctypes.c_int, [_p, _u64, ctypes.POINTER(_u64)]),
+        "sieve_ext_limit": (ctypes.c_int, [_p, ctypes.POINTER(_u64)]),
+        "sieve_count_wide": (ctypes.c_int, [_p, ctypes.POINTER(U128), ctypes.POINTER(U128),
+                                            ctypes.POINTER(_u64), _p]),
+        "sieve_list_wide": (ctypes.c_int, [_p, ctypes.POINTER(U128), ctypes.POINTER(U128), _p, _u64,
+                                           ctypes.POINTER(_u64), _p]),
         "sieve_wheel_start": (ctypes.c_int, [_u64, _u64, _u64, ctypes.POINTER(ctypes.c_int64),
                                              ctypes.POINTER(ctypes.c_int64)]),
         "sieve_plan_range": (ctypes.c_int, [_u64, _u64, ctypes.c_uint32, ctypes.POINTER(_u64),
@@ -176,6 +197,23 @@ def _check(code: int, what: str) -> None:
 def list_bound(lo: int, hi: int) -> int:
     """Rigorous upper bound on the number of primes in [lo, hi)."""
     return int(load_library().sieve_list_bound(lo, hi))
+
+
+def list_bound_wide(lo: int, hi: int) -> int:
+    """The bound of list_bound for a wide window: it depends only on lo mod 6
+    and hi - lo, so it is taken on a window of the same shape below 2^63."""
+    if hi <= lo:
+        return 0
+    base = 6 << 37
+    return list_bound(base + lo % 6, base + lo % 6 + (hi - lo))
+
+
+def wide_values(t) -> list:
+    """Python ints from a wide list (a tensor or array of shape (n, 2) whose
+    rows hold the low and high 64-bit halves)."""
+    a = t.cpu().numpy() if hasattr(t, "cpu") else np.asarray(t)
+    a = a.view(np.uint64).reshape(-1, 2)
+    return [int(h) << 64 | int(lo) for lo, h in a]
 
 
 def wheel_start(p: int, base: int, M: int) -> tuple[int, int]:
@@ -315,6 +353,58 @@ class Sieve:
         need = math.isqrt(max(hi - 1, 0))
         if need > self.base_limit:
             self.base_primes(need)
+
+    @property
+    def ext_limit(self) -> int:
+        v = _u64()
+        _check(self._lib.sieve_ext_limit(self._h, ctypes.byref(v)), "sieve_ext_limit")
+        return v.value
+
+    def base_primes_wide(self, limit: int) -> int:
+        """Makes all primes <= limit (<= 2^36) available to the wide calls:
+        resident below 2^32, an extension list above; returns how many."""
+        n = _u64()
+        _check(self._lib.sieve_base_primes_wide(self._h, limit, ctypes.byref(n)), "sieve_base_primes_wide")
+        return n.value
+
+    def ensure_base_wide_for(self, hi: int) -> None:
+        """Makes the wide calls' base primes cover isqrt(hi - 1)."""
+        import math
+        need = math.isqrt(max(hi - 1, 0))
+        if need > 1 << 32:  # 2^32 itself is not prime
+            if need > self.ext_limit:
+                self.base_primes_wide(need)
+        elif min(need, (1 << 32) - 1) > self.base_limit:
+            self.base_primes(min(need, (1 << 32) - 1))
+
+    def count_wide(self, lo: int, hi: int, stream=None) -> int:
+        """Number of primes in [lo, hi), 2^40 <= lo, hi - lo <= 2^40, values up
+        to 2^128 (the base primes must cover isqrt(hi - 1))."""
+        c = _u64()
+        a, b = U128.of(lo), U128.of(hi)
+        _check(self._lib.sieve_count_wide(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                          _stream_handle(stream)), "sieve_count_wide")
+        return c.value
+
+    def list_wide(self, lo: int, hi: int, out=None, stream=None):
+        """Primes of the window [lo, hi) as an int64 tensor of shape (n, 2) on
+        the context's GPU: row k holds the low and high 64-bit halves of the
+        k-th prime (bit for bit).  With `out` (shape (cap, 2), int64) given,
+        a view of its filled prefix is returned."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty((max(list_bound_wide(lo, hi), 1), 2), dtype=torch.int64,
+                              device="cuda:%d" % self.device)
+        if out.dtype != torch.int64 or out.dim() != 2 or out.shape[1] != 2 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int64 tensor of shape (cap, 2)")
+        n = _u64()
+        a, b = U128.of(lo), U128.of(hi)
+        code = self._lib.sieve_list_wide(self._h, ctypes.byref(a), ctypes.byref(b), out.data_ptr(),
+                                         out.shape[0], ctypes.byref(n), _stream_handle(stream))
+        if code == SIEVE_E_CAPACITY:
+            raise SieveError(code, "sieve_list_wide needs %d elements" % n.value)
+        _check(code, "sieve_list_wide")
+        return out[: n.value]
 
     def count(self, lo: int, hi: int) -> int:
         c = _u64()

@@ -23,7 +23,7 @@ LIB = os.path.join(HERE, "libsieve.so")
 LIB_MARKCOUNT = os.path.join(HERE, "libsieve_markcount.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.hip", "kernels.hip", "server.hip", "stream.hip", "lds_probe.hip"]
+SOURCES = ["api.hip", "kernels.hip", "server.hip", "stream.hip", "lds_probe.hip", "wide.hip"]
 
 COMMON = [
     "--offload-arch=gfx950",

@@ -774,6 +774,7 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed, boo
     k.chunk_vbase = c->d_chunk_vbase.p;
     k.bitmap = c->d_bitmap.p;
     k.chunk_off = c->d_chunk_off.p;
+    k.wbase_lo = k.wbase_hi = 0;
     if (lists && (e = launch_compact(k, (uint32_t)c->cus * 4, s)) != hipSuccess)
         return e;
     if (timed && (e = hipEventRecord(c->ev[2], s)) != hipSuccess)
@@ -1259,6 +1260,8 @@ void destroy_ctx(sieve_ctx *c)
     c->d_items.release();
     c->d_item_prefix.release();
     c->d_pstab.release();
+    c->d_ext.release();
+    c->d_wr.release();
     c->d_blob.release();
     c->d_counters.release();
     c->d_counts.release();
@@ -1321,6 +1324,12 @@ int run_job(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, co
     return ::run_job(c, n, lo, hi, mode, off, cap, elem_bytes, out, counts, status, stream, use_graph, async_ok);
 }
 int grow_base_primes(sieve_ctx *c, uint64_t limit) { return ::grow_base_primes(c, limit); }
+int ensure_capacity(sieve_ctx *c, uint64_t nranges, uint64_t nchunks, uint64_t ntiles, uint64_t gtiles)
+{
+    return ::ensure_capacity(c, nranges, nchunks, ntiles, gtiles);
+}
+size_t blob_ranges_offset() { return blob_layout(1).ranges; }
+uint32_t primes_upto(const sieve_ctx *c, uint64_t x) { return ::primes_upto(c, x); }
 }  // namespace rt
 }  // namespace sieve
 

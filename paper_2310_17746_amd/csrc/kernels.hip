@@ -1207,9 +1207,11 @@ __global__ void __launch_bounds__(kFinalizeThreads) k_finalize(FinalizeArgs a)
 
     for (uint32_t r = blockIdx.x; r < nranges; r += gridDim.x) {
         const RangeDesc &d = a.ranges[r];
-        // 2 and 3 lie outside the wheel (Sec. 2.1) and are reported when in range.
-        const uint32_t has2 = (d.lo <= 2 && 2 < d.hi) ? 1u : 0u;
-        const uint32_t has3 = (d.lo <= 3 && 3 < d.hi) ? 1u : 0u;
+        // 2 and 3 lie outside the wheel (Sec. 2.1) and are reported when in
+        // range (a wide window's bounds are offsets from a base above both).
+        const bool abs_vals = a.job->wide == 0;
+        const uint32_t has2 = (abs_vals && d.lo <= 2 && 2 < d.hi) ? 1u : 0u;
+        const uint32_t has3 = (abs_vals && d.lo <= 3 && 3 < d.hi) ? 1u : 0u;
         const uint32_t sp = has2 + has3;
         if (d.mode == 0) {
             if (tid == 0) {
@@ -1339,6 +1341,26 @@ __device__ __forceinline__ void wave_lds_fence()
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 }
 
+// Stores output element i for value offset v from the chunk bases: the
+// value itself, or for 128-bit elements the window base plus v (one 16-byte
+// store).
+template <typename T>
+__device__ __forceinline__ void put_out(__attribute__((address_space(1))) T *out, uint64_t i, uint64_t v,
+                                        const CompactArgs &)
+{
+    out[i] = (T)v;
+}
+
+template <>
+__device__ __forceinline__ void put_out<U128>(__attribute__((address_space(1))) U128 *out, uint64_t i, uint64_t v,
+                                              const CompactArgs &a)
+{
+    typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+    const uint64_t lo = a.wbase_lo + v;
+    const uint64_t hi = a.wbase_hi + (lo < v ? 1u : 0u);
+    ((__attribute__((address_space(1))) u64x2 *)out)[i] = u64x2{lo, hi};
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kCompactThreads) k_compact(CompactArgs a)
 {
@@ -1440,7 +1462,7 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(CompactArgs a)
                 }
                 wave_lds_fence();  // the window is written before any lane reads it
                 for (uint32_t e = lane; e < wtot; e += kWave)
-                    out[obase + e] = (T)(cvb + s_stage[wave][e]);
+                    put_out<T>(out, obase + e, cvb + s_stage[wave][e], a);
                 wave_lds_fence();  // and read before the next chunk rewrites it
             } else {
                 // Passes over rank windows of kStagePerWave, uniform across the wavefront.
@@ -1459,7 +1481,7 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(CompactArgs a)
                     wave_lds_fence();
                     const uint32_t n_in = (wtot - pass) < kStagePerWave ? (wtot - pass) : kStagePerWave;
                     for (uint32_t e = lane; e < n_in; e += kWave)
-                        out[obase + pass + e] = (T)(cvb + s_stage[wave][e]);
+                        put_out<T>(out, obase + pass + e, cvb + s_stage[wave][e], a);
                     wave_lds_fence();
                 }
             }
@@ -1629,6 +1651,13 @@ hipError_t launch_compact(const CompactArgs &a, uint32_t grid, hipStream_t s)
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL(k_compact<uint64_t>, dim3(grid), dim3(kCompactThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+// The compaction of a wide window (16-byte elements).
+hipError_t launch_compact_wide(const CompactArgs &a, uint32_t grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_compact<U128>, dim3(grid), dim3(kCompactThreads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -157,6 +157,15 @@ struct sieve_ctx {
     unsigned long long *h_tally = nullptr;
     unsigned long long tally_total[4] = {0, 0, 0, 0};
 
+    // Windows beyond 64 bits (wide.hip): extension base primes from 2^32 up
+    // to ext_limit (ascending, 64-bit), every kExtSample-th of them on the
+    // host for counting the ones below a bound, and the per-window residues
+    // (W - 1) mod P of the primes marked in LDS.
+    sieve::rt::DevBuf<uint64_t> d_ext;
+    uint64_t n_ext = 0, ext_limit = 0;
+    std::vector<uint64_t> h_ext_sample;
+    sieve::rt::DevBuf<uint32_t> d_wr;
+
     // Device address of this GPU's fixed scratch array (allocation-free
     // entry point), looked up once when the context is created.
     unsigned char *static_scratch = nullptr;
@@ -186,6 +195,12 @@ int run_job(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, co
             hipStream_t stream, bool use_graph, bool async_ok = false);
 // Makes the resident base primes cover `limit`.
 int grow_base_primes(sieve_ctx *c, uint64_t limit);
+// Makes the job scratch hold a job of the given size (capacities only grow).
+int ensure_capacity(sieve_ctx *c, uint64_t nranges, uint64_t nchunks, uint64_t ntiles, uint64_t gtiles);
+// Byte offset of the RangeDesc table in the device blob (after the JobHeader).
+size_t blob_ranges_offset();
+// Number of resident base primes <= x (x <= c->limit).
+uint32_t primes_upto(const sieve_ctx *c, uint64_t x);
 
 }  // namespace rt
 }  // namespace sieve

@@ -74,7 +74,7 @@ struct JobHeader {
     uint64_t nchunks;    // bitmap chunks over all list ranges
     uint64_t nunits;     // bucket work units over all ranges
     uint32_t bmode;      // bucket layout: 1 estimated per-range slices, 2 exact per-tile offsets
-    uint32_t pad0;
+    uint32_t wide;       // 1: a window beyond 64 bits, in offsets from its base (no 2 or 3)
     uint32_t nranges;
     uint32_t nlist;      // list ranges
     void *out;           // caller's output buffer (list ranges)
@@ -205,6 +205,12 @@ struct CompactArgs {
     const unsigned long long *bitmap;
     const unsigned long long *chunk_off;    // per chunk: first output element; ~0 when
                                             // its range does not fit (nothing is written)
+    uint64_t wbase_lo, wbase_hi;            // 128-bit output: the window base added to every value
+};
+
+// A 128-bit output element (low half first), as sieve_u128 in sieve.h.
+struct alignas(16) U128 {
+    uint64_t lo, hi;
 };
 
 }  // namespace sieve

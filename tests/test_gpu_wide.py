@@ -1,0 +1,147 @@
+"""Windows beyond the 64-bit calls' domain (Sec. 6: ranges past 2^64 are the
+method's next step): sieve_count_wide / sieve_list_wide against the wide
+oracle (unsigned 128-bit arithmetic, pinned by deterministic Miller-Rabin),
+element by element.
+
+Windows span several tiles with ragged ends, just above 2^64, straddling
+2^64, between 2^63 (the end of the 64-bit calls' domain) and 2^64, at the
+lowest allowed base 2^40 (where the 64-bit path gives the same list), and
+past 2^66, where the base primes reach beyond 2^32 into the 64-bit extension
+list.  Edge cases: empty windows, windows with no wheel value, the argument
+limits, missing base primes and a short output buffer.
+"""
+import math
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+pkg = pytest.importorskip("paper_2310_17746_amd")
+
+T64 = 1 << 64
+
+
+@pytest.fixture(scope="module")
+def sv():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    s = pkg.Sieve(0)
+    print("wide: resident base primes below 2^32", flush=True)
+    s.base_primes((1 << 32) - 1)
+    yield s
+    s.close()
+
+
+def _check_window(sv, lo, hi):
+    print("wide: list [%d, %d)" % (lo, hi), flush=True)
+    got = sv.list_wide(lo, hi)
+    want = oracle.primes_wide(lo, hi)
+    g = got.cpu().numpy().view(np.uint64).reshape(-1, 2)
+    assert g.shape == want.shape, (lo, hi, g.shape, want.shape)
+    if len(want):
+        bad = np.nonzero((g != want).any(axis=1))[0]
+        assert len(bad) == 0, (lo, hi, int(bad[0]), g[bad[0]], want[bad[0]])
+    assert sv.count_wide(lo, hi) == len(want)
+    return g
+
+
+WINDOWS = [
+    (T64, T64 + 10 ** 7),                                  # three tiles, ragged last one
+    (T64 + 12345, T64 + 12345 + 3 * 10 ** 6 + 7),          # ragged both ends
+    (T64 - 4 * 10 ** 6 - 1, T64 + 4 * 10 ** 6 + 3),        # straddles 2^64
+    ((1 << 63) + 5, (1 << 63) + 2 * 10 ** 6),              # past the 64-bit calls' end
+]
+
+
+@pytest.mark.parametrize("lo,hi", WINDOWS)
+def test_list_wide_matches_oracle(sv, lo, hi):
+    _check_window(sv, lo, hi)
+
+
+def test_wide_at_2_40_equals_64bit_path(sv):
+    lo, hi = 1 << 40, (1 << 40) + 5 * 10 ** 6 + 1
+    g = _check_window(sv, lo, hi)
+    assert np.all(g[:, 1] == 0)
+    narrow = sv.list(lo, hi, elem_bytes=8).cpu().numpy().view(np.uint64)
+    assert np.array_equal(g[:, 0], narrow)
+
+
+def test_count_wide_large_window(sv):
+    lo, hi = T64 + 10 ** 9, T64 + 10 ** 9 + 10 ** 8
+    print("wide: count [%d, %d)" % (lo, hi), flush=True)
+    assert sv.count_wide(lo, hi) == oracle.count_wide(lo, hi)
+
+
+def test_tiny_and_empty_windows(sv):
+    base = T64 + 6000
+    base -= base % 6
+    for a in range(0, 8):
+        for b in range(a, 14):
+            lo, hi = base + a, base + b
+            want = [p for p in range(lo, hi) if brute.is_prime_mr(p)]
+            assert sv.count_wide(lo, hi) == len(want), (a, b)
+            got = pkg.wide_values(sv.list_wide(lo, hi))
+            assert got == want, (a, b)
+
+
+def test_argument_limits(sv):
+    with pytest.raises(pkg.SieveError) as e:
+        sv.count_wide((1 << 40) - 1, 1 << 41)
+    assert e.value.code == pkg.SIEVE_E_INVAL
+    with pytest.raises(pkg.SieveError) as e:
+        sv.count_wide(T64, T64 + (1 << 40) + 1)
+    assert e.value.code == pkg.SIEVE_E_INVAL
+    with pytest.raises(pkg.SieveError) as e:
+        sv.count_wide(T64 + 10, T64 + 9)
+    assert e.value.code == pkg.SIEVE_E_INVAL
+    # base primes end below 2^32 and no extension list: 2^66 needs primes to 2^33
+    with pytest.raises(pkg.SieveError) as e:
+        sv.count_wide(1 << 66, (1 << 66) + 100)
+    assert e.value.code == pkg.SIEVE_E_RANGE
+    with pytest.raises(pkg.SieveError) as e:
+        sv.base_primes_wide(pkg.WIDE_MAX_BASE + 1)
+    assert e.value.code == pkg.SIEVE_E_INVAL
+
+
+def test_short_output_reports_capacity(sv):
+    lo, hi = T64, T64 + 10 ** 5
+    n = sv.count_wide(lo, hi)
+    out = torch.empty((n - 1, 2), dtype=torch.int64, device="cuda")
+    with pytest.raises(pkg.SieveError) as e:
+        sv.list_wide(lo, hi, out=out)
+    assert e.value.code == pkg.SIEVE_E_CAPACITY
+    out = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+    assert sv.list_wide(lo, hi, out=out).shape[0] == n
+
+
+def test_missing_base_primes_is_range_error():
+    with pkg.Sieve(0) as s:
+        s.base_primes(1 << 20)
+        with pytest.raises(pkg.SieveError) as e:
+            s.count_wide(T64, T64 + 1000)
+        assert e.value.code == pkg.SIEVE_E_RANGE
+
+
+def test_extension_primes_past_2_66(sv):
+    lo, hi = (1 << 66) - 10 ** 6 - 3, (1 << 66) + 10 ** 6
+    root = math.isqrt(hi - 1)
+    print("wide: extension primes to %d" % root, flush=True)
+    n = sv.base_primes_wide(root)
+    assert sv.ext_limit == root
+    assert n == oracle.count(5, root + 1)  # resident and extension primes >= 5
+    g = _check_window(sv, lo, hi)
+    _check_window(sv, 3 * T64 + 7, 3 * T64 + 7 + 5 * 10 ** 5)  # high half 3
+    # independent spot check: deterministic Miller-Rabin on sampled wheel values
+    vals = set(int(h) << 64 | int(l) for l, h in g)
+    rng = random.Random(7)
+    for _ in range(300):
+        v = rng.randrange(lo, hi)
+        v += (1 - v % 6) % 6
+        if v < hi:
+            assert (v in vals) == brute.is_prime_mr(v), v
