@@ -228,13 +228,12 @@ __device__ __forceinline__ void mark_plane_fixed_skip5(uint32_t start, uint32_t 
             a += s5;
         }
     }
-    for (uint32_t n = 0; n < 5; ++n) {
-        const uint32_t x = a + n * sb;
-        if (x >= end)
-            break;
+    // The rest, hit by hit: a whole period when the loop ran (it stops with
+    // a + 4 sb >= end), else every hit (with sb = floor(end / 5) and end not
+    // a multiple of 5 there can be six).
+    for (uint32_t n = 0; a < end; a += sb, n = n == 4 ? 0u : n + 1u)
         if (n != s)
-            lds_or(x, mask, t);
-    }
+            lds_or(a, mask, t);
 }
 
 // As mark_plane, for a lane whose hits n = 0, 1, 2, ... have cofactors
@@ -270,13 +269,11 @@ __device__ __forceinline__ void mark_plane_skip5(uint32_t base, uint64_t start, 
             i += 5 * step;
         }
     }
-    for (uint32_t n = 0; n < 5; ++n) {
-        const uint64_t x = (uint64_t)i + (uint64_t)n * step;
-        if (x >= nbits)
-            break;
+    // The rest, hit by hit (as in mark_plane_fixed_skip5: up to six when
+    // the loop did not run).
+    for (uint32_t n = 0; i < nbits; i += step, n = n == 4 ? 0u : n + 1u)
         if (n != s)
-            lds_or((((uint32_t)x >> 3) & ~3u) + base, 1u << ((uint32_t)x & 31), t);
-    }
+            lds_or(((i >> 3) & ~3u) + base, 1u << (i & 31), t);
 }
 
 // Residue mod 5 of the cofactor m of the value B + 6*id + r = m * P, from

@@ -59,7 +59,10 @@ def _expected_hits(lo, hi):
 
 
 RANGES = [(10 ** 6, 10 ** 6 + 3 * 10 ** 7), (2, 10 ** 9 + 1), (10 ** 12, 10 ** 12 + 10 ** 8),
-          (10 ** 13 + 7, 10 ** 13 + 4 * 10 ** 8 + 3), (10 ** 15, 10 ** 15 + 10 ** 6)]
+          (10 ** 13 + 7, 10 ** 13 + 4 * 10 ** 8 + 3), (10 ** 15, 10 ** 15 + 10 ** 6),
+          # last tile of 2306 words: a fixed-mask lane of 461 (32 lanes) has
+          # step floor(plane bytes / 5) and a sixth hit in the last word
+          (49944454, 87742652)]
 
 
 @pytest.mark.parametrize("params", [
