@@ -357,8 +357,10 @@ def bench_serve(pkg, workloads):
             "long_job_count": int(done[n]["count"]),
             "ints_per_s": round((ints + long_hi - long_lo) / span, 1),
             "req_per_s": round(n / span, 1),
-            "utilization": round(st["busy_ns"] / max(st["elapsed_ns"], 1), 4),
-            "steps": st["steps"]}
+            # device time of the steps' jobs over the span from the first
+            # arrival to the last completion
+            "utilization": round(st["busy_ns"] / max(span * 1e9, 1), 4),
+            "steps": st["steps"], "overlap_steps": st["overlap_steps"]}
 
 
 def cpu_model() -> str:

@@ -468,11 +468,12 @@ typedef struct sieve_server_stats {
     uint64_t tiles;           /* tiles sieved */
     uint64_t ints;            /* integers sieved */
     uint64_t completed;       /* requests completed (any status) */
-    uint64_t busy_ns;         /* time with a step on the device */
+    uint64_t busy_ns;         /* device time of the steps' jobs (events around each job) */
     uint64_t elapsed_ns;      /* time since creation */
     uint64_t arena_peak_bytes;
     uint64_t queued, active;  /* at the time of the call */
     uint64_t bucket_steps;    /* steps whose job used the bucket sieve */
+    uint64_t overlap_steps;   /* steps enqueued while the previous step was still running */
 } sieve_server_stats;
 
 /* Creates a server on ctx (p == NULL: defaults).  *srv is set on success. */

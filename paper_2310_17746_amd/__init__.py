@@ -103,7 +103,7 @@ class Completion(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in ("steps", "tiles", "ints", "completed", "busy_ns",
                                                "elapsed_ns", "arena_peak_bytes", "queued", "active",
-                                               "bucket_steps")]
+                                               "bucket_steps", "overlap_steps")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -9,6 +9,12 @@
 // [lo, hi) are themselves ranges whose tiles coincide with the request's own
 // tiles, so counts add up and list pieces concatenate in order: a request's
 // result equals the stand-alone result for its range.
+//
+// Steps are pipelined: step k + 1 is planned on the host and enqueued as a
+// stream-ordered job while step k runs, and only then are step k's results
+// applied.  A list request has at most one piece in flight (its next piece's
+// output offset is the count so far); count requests take a piece in every
+// step.  Device busy time comes from events around each step's job.
 #include <stdint.h>
 #include <string.h>
 
@@ -94,7 +100,11 @@ struct Request {
     uint64_t t_arr = 0, t_admit = 0;
     uint64_t ntiles = 0, base = 0;
     uint32_t last_words = 0;
-    uint64_t next_tile = 0;
+    uint64_t next_tile = 0;   // first tile not yet handed to a step
+    uint64_t tiles_done = 0;  // tiles of the pieces whose results are in
+    uint32_t inflight = 0;    // pieces in enqueued steps
+    uint32_t issued = 0;      // pieces handed out so far
+    int err = SIEVE_OK;       // first failed piece's status
     uint64_t count = 0;
     uint64_t off_bytes = 0, cap_elems = 0, arena_bytes = 0;
     bool has_arena = false;
@@ -161,6 +171,88 @@ void complete_locked(sieve_server *s, Request *r, int status, uint64_t t)
     delete r;
 }
 
+// One scheduler step: the pieces of one batched job, their results, and
+// events around the job on the context stream.
+struct Step {
+    std::vector<uint64_t> lo, hi, off, cap, counts;
+    std::vector<uint8_t> mode;
+    std::vector<int32_t> status;
+    std::vector<std::pair<Request *, uint64_t>> pieces;  // request, tiles taken
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool in_flight = false, timed = false;
+    int rc = SIEVE_OK;
+    bool buckets = false;  // the step's job ran the bucket sieve
+};
+
+bool request_done(const Request *r)
+{
+    return r->ntiles == 0 ? r->issued > 0 : r->tiles_done >= r->ntiles;
+}
+
+// Whether r may take a piece in the step being planned.
+bool plannable(const Request *r)
+{
+    if (r->cancelled || r->err != SIEVE_OK || (r->mode && r->inflight))
+        return false;
+    return r->ntiles == 0 ? r->issued == 0 : r->next_tile < r->ntiles;
+}
+
+// Applies a finished step's results and completes the requests it ends.
+void apply_step(sieve_server *s, Step &st)
+{
+    float ms = 0;
+    const bool have_ms = st.timed && hipEventElapsedTime(&ms, st.ev0, st.ev1) == hipSuccess;
+    const uint64_t te = s->now();
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->st.steps++;
+    if (have_ms)
+        s->st.busy_ns += (uint64_t)((double)ms * 1e6);
+    if (st.buckets)
+        s->st.bucket_steps++;
+    for (size_t i = 0; i < st.pieces.size(); ++i) {
+        Request *r = st.pieces[i].first;
+        r->inflight--;
+        const int stt = st.rc != SIEVE_OK ? st.rc : st.status[i];
+        s->st.tiles += st.pieces[i].second;
+        s->st.ints += st.hi[i] - st.lo[i];
+        if (stt == SIEVE_OK) {
+            r->count += st.counts[i];
+            r->tiles_done += st.pieces[i].second;
+        } else if (r->err == SIEVE_OK) {
+            r->err = stt;
+        }
+        if (r->inflight)
+            continue;
+        int fin = 1;  // 1: not finished
+        if (r->err != SIEVE_OK)
+            fin = r->err;
+        else if (request_done(r))
+            fin = SIEVE_OK;
+        else if (r->cancelled)
+            fin = SIEVE_E_CANCELLED;
+        if (fin != 1) {
+            s->active.erase(std::find(s->active.begin(), s->active.end(), r));
+            complete_locked(s, r, fin, te);
+        }
+    }
+    st.in_flight = false;
+    st.pieces.clear();
+    s->cv_done.notify_all();
+}
+
+// Waits for an enqueued step and applies it.
+void finish_step(sieve_server *s, Step &st)
+{
+    if (!st.in_flight)
+        return;
+    if (st.timed && hipEventSynchronize(st.ev1) != hipSuccess) {
+        (void)hipGetLastError();
+        if (st.rc == SIEVE_OK)
+            st.rc = SIEVE_E_DEVICE;
+    }
+    apply_step(s, st);
+}
+
 void scheduler(sieve_server *s)
 {
     sieve_ctx *c = s->ctx;
@@ -168,18 +260,25 @@ void scheduler(sieve_server *s)
     const uint32_t pw = c->prm.segment_bytes / 8;
     const uint64_t S = 192ull * pw;  // integers per tile
     const uint32_t eb = s->p.elem_bytes;
-    std::vector<uint64_t> lo, hi, off, cap, counts;
-    std::vector<uint8_t> mode;
-    std::vector<int32_t> status;
-    std::vector<std::pair<Request *, uint64_t>> pieces;  // request, tiles taken
+    Step steps[2];
+    for (Step &st : steps) {
+        if (hipEventCreate(&st.ev0) != hipSuccess || hipEventCreate(&st.ev1) != hipSuccess)
+            (void)hipGetLastError();
+    }
+    int cur = 0;  // steps[cur] is planned next; steps[cur ^ 1] may be in flight
 
     for (;;) {
         uint64_t need_limit = 0;
+        Step &st = steps[cur];
+        Step &prev = steps[cur ^ 1];
+        bool quit = false;
         {
             std::unique_lock<std::mutex> lk(s->mu);
             for (;;) {
-                if (s->stop)
-                    return;
+                if (s->stop) {
+                    quit = true;
+                    break;
+                }
                 const uint64_t t = s->now();
                 while (!s->inbox.empty() && s->inbox.begin()->first <= t) {
                     s->pending.push_back(s->inbox.begin()->second);
@@ -211,16 +310,20 @@ void scheduler(sieve_server *s)
                     if (r->hi > 4)
                         need_limit = std::max(need_limit, sieve::rt::isqrt_host(r->hi - 1));
                 }
-                // Drop cancelled active requests.
+                // Drop cancelled active requests that have no piece in flight.
                 for (size_t i = 0; i < s->active.size();) {
-                    if (s->active[i]->cancelled) {
-                        complete_locked(s, s->active[i], SIEVE_E_CANCELLED, t);
+                    Request *r = s->active[i];
+                    if (r->cancelled && r->inflight == 0) {
+                        complete_locked(s, r, SIEVE_E_CANCELLED, t);
                         s->active.erase(s->active.begin() + i);
                     } else {
                         ++i;
                     }
                 }
-                if (!s->active.empty())
+                bool work = false;
+                for (const Request *r : s->active)
+                    work = work || plannable(r);
+                if (work || prev.in_flight)
                     break;
                 s->cv_done.notify_all();
                 if (!s->inbox.empty()) {
@@ -230,66 +333,79 @@ void scheduler(sieve_server *s)
                     s->cv_work.wait(lk);
                 }
             }
-            // Build one step: round-robin pieces of the active requests.
-            lo.clear();
-            hi.clear();
-            off.clear();
-            cap.clear();
-            mode.clear();
-            pieces.clear();
-            uint64_t budget = s->p.step_tiles;
-            const size_t n = s->active.size();
-            for (size_t k = 0; k < n && budget; ++k) {
-                Request *r = s->active[(s->rr + k) % n];
-                const uint64_t left = r->ntiles - r->next_tile;
-                uint64_t take = std::min<uint64_t>(std::min<uint64_t>(left, s->p.quantum_tiles), budget);
-                if (r->ntiles == 0)
-                    take = 0;  // no wheel values: one tile-less piece counts 2 and 3
-                else if (take == 0)
-                    continue;
-                const uint64_t k0 = r->next_tile, k1 = k0 + take;
-                lo.push_back(k0 == 0 ? r->lo : r->base + k0 * S);
-                hi.push_back(r->ntiles == 0 || k1 == r->ntiles ? r->hi : r->base + k1 * S);
-                mode.push_back((uint8_t)r->mode);
-                off.push_back(r->mode ? r->off_bytes / eb + r->count : 0);
-                cap.push_back(r->mode ? r->cap_elems - r->count : 0);
-                pieces.emplace_back(r, take);
-                budget -= take;
-            }
-            s->rr = n ? (s->rr + 1) % n : 0;
-        }
-        int rc = SIEVE_OK;
-        if (need_limit > c->limit)
-            rc = sieve::rt::grow_base_primes(c, need_limit);
-        const uint64_t m = lo.size();
-        counts.assign(m, 0);
-        status.assign(m, 0);
-        const uint64_t tb = s->now();
-        const uint64_t bj = c->bucket_jobs;
-        if (rc == SIEVE_OK && m)
-            rc = sieve::rt::run_job(c, m, lo.data(), hi.data(), mode.data(), off.data(), cap.data(), (int)eb,
-                                    s->arena_base, counts.data(), status.data(), nullptr, c->prm.use_graph != 0);
-        const uint64_t te = s->now();
-        {
-            std::lock_guard<std::mutex> lk(s->mu);
-            s->st.steps++;
-            s->st.busy_ns += te - tb;
-            if (c->bucket_jobs != bj)
-                s->st.bucket_steps++;
-            for (uint64_t i = 0; i < m; ++i) {
-                Request *r = pieces[i].first;
-                s->st.tiles += pieces[i].second;
-                s->st.ints += hi[i] - lo[i];
-                int stt = rc != SIEVE_OK ? rc : status[i];
-                r->count += counts[i];
-                r->next_tile += pieces[i].second;
-                if (stt != SIEVE_OK || r->next_tile >= r->ntiles) {
-                    s->active.erase(std::find(s->active.begin(), s->active.end(), r));
-                    complete_locked(s, r, stt, te);
+            if (!quit) {
+                // Plan one step: round-robin pieces of the plannable requests.
+                st.lo.clear();
+                st.hi.clear();
+                st.off.clear();
+                st.cap.clear();
+                st.mode.clear();
+                st.pieces.clear();
+                uint64_t budget = s->p.step_tiles;
+                const size_t n = s->active.size();
+                for (size_t k = 0; k < n && budget; ++k) {
+                    Request *r = s->active[(s->rr + k) % n];
+                    if (!plannable(r))
+                        continue;
+                    // a request without wheel values takes one tile-less piece (2 and 3)
+                    const uint64_t left = r->ntiles - r->next_tile;
+                    const uint64_t take =
+                        r->ntiles == 0 ? 0 : std::min<uint64_t>(std::min<uint64_t>(left, s->p.quantum_tiles), budget);
+                    const uint64_t k0 = r->next_tile, k1 = k0 + take;
+                    st.lo.push_back(k0 == 0 ? r->lo : r->base + k0 * S);
+                    st.hi.push_back(r->ntiles == 0 || k1 == r->ntiles ? r->hi : r->base + k1 * S);
+                    st.mode.push_back((uint8_t)r->mode);
+                    st.off.push_back(r->mode ? r->off_bytes / eb + r->count : 0);
+                    st.cap.push_back(r->mode ? r->cap_elems - r->count : 0);
+                    st.pieces.emplace_back(r, take);
+                    r->next_tile = k1;
+                    r->inflight++;
+                    r->issued++;
+                    budget -= take;
                 }
+                s->rr = n ? (s->rr + 1) % n : 0;
             }
-            s->cv_done.notify_all();
         }
+        if (quit) {
+            // Let enqueued work end before the context is handed back.
+            finish_step(s, prev);
+            break;
+        }
+        const uint64_t m = st.lo.size();
+        st.rc = SIEVE_OK;
+        if (need_limit > c->limit) {
+            // The base primes are re-installed: no step may be reading them.
+            finish_step(s, prev);
+            st.rc = sieve::rt::grow_base_primes(c, need_limit);
+        }
+        if (m) {
+            st.counts.assign(m, 0);
+            st.status.assign(m, 0);
+            const uint64_t bj = c->bucket_jobs;
+            if (prev.in_flight) {
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->st.overlap_steps++;
+            }
+            st.timed = st.ev0 && st.ev1 && hipEventRecord(st.ev0, c->stream) == hipSuccess;
+            if (st.rc == SIEVE_OK)
+                st.rc = sieve::rt::run_job(c, m, st.lo.data(), st.hi.data(), st.mode.data(), st.off.data(),
+                                           st.cap.data(), (int)eb, s->arena_base, st.counts.data(),
+                                           st.status.data(), c->stream, c->prm.use_graph != 0, true);
+            st.buckets = c->bucket_jobs != bj;
+            st.timed = st.timed && hipEventRecord(st.ev1, c->stream) == hipSuccess;
+            if (!st.timed)
+                (void)hipStreamSynchronize(c->stream);
+            st.in_flight = true;
+        }
+        // The previous step ends while this one waits behind it on the device.
+        finish_step(s, prev);
+        cur ^= 1;
+    }
+    for (Step &st : steps) {
+        if (st.ev0)
+            (void)hipEventDestroy(st.ev0);
+        if (st.ev1)
+            (void)hipEventDestroy(st.ev1);
     }
 }
 
