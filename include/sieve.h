@@ -445,10 +445,12 @@ typedef struct sieve_server_params {
     uint64_t out_budget_bytes; /* device output arena; default 1 GiB */
     uint32_t max_active;       /* requests on the device at once; default 1024 */
     uint32_t step_tiles;       /* tiles per scheduler step; default 16 per CU */
-    uint32_t quantum_tiles;    /* tiles per request per step; default step_tiles / 8 */
+    uint32_t quantum_tiles;    /* tiles per request per step; default step_tiles / 16 */
     uint32_t elem_bytes;       /* list element size, 4 or 8; default 8 */
     uint32_t max_queue;        /* submitted but not admitted; default 1 << 20 */
-    uint32_t reserved;
+    uint32_t overlap;          /* 1: step k + 1 is planned and enqueued while step k runs
+                                  (hides host planning, costs arrivals one step of waiting);
+                                  0 (default): one step on the device at a time */
 } sieve_server_params;
 
 /* One finished request.  Times are nanoseconds on the server's steady clock

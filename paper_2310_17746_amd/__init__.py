@@ -87,7 +87,7 @@ class ServerParams(ctypes.Structure):
     _fields_ = [("out_budget_bytes", ctypes.c_uint64), ("max_active", ctypes.c_uint32),
                 ("step_tiles", ctypes.c_uint32), ("quantum_tiles", ctypes.c_uint32),
                 ("elem_bytes", ctypes.c_uint32), ("max_queue", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("overlap", ctypes.c_uint32)]
 
 
 class Completion(ctypes.Structure):

@@ -10,11 +10,13 @@
 // tiles, so counts add up and list pieces concatenate in order: a request's
 // result equals the stand-alone result for its range.
 //
-// Steps are pipelined: step k + 1 is planned on the host and enqueued as a
-// stream-ordered job while step k runs, and only then are step k's results
-// applied.  A list request has at most one piece in flight (its next piece's
-// output offset is the count so far); count requests take a piece in every
-// step.  Device busy time comes from events around each step's job.
+// With overlap on, steps are pipelined: step k + 1 is planned on the host
+// and enqueued as a stream-ordered job while step k runs, and only then are
+// step k's results applied.  A list request has at most one piece in flight
+// (its next piece's output offset is the count so far); count requests take
+// a piece in every step.  Off (the default), each step's job finishes before
+// the next is planned, so a request that arrives during a step joins the
+// next one.  Device busy time comes from events around each step's job.
 #include <stdint.h>
 #include <string.h>
 
@@ -390,12 +392,15 @@ void scheduler(sieve_server *s)
             if (st.rc == SIEVE_OK)
                 st.rc = sieve::rt::run_job(c, m, st.lo.data(), st.hi.data(), st.mode.data(), st.off.data(),
                                            st.cap.data(), (int)eb, s->arena_base, st.counts.data(),
-                                           st.status.data(), c->stream, c->prm.use_graph != 0, true);
+                                           st.status.data(), c->stream, c->prm.use_graph != 0,
+                                           s->p.overlap != 0);
             st.buckets = c->bucket_jobs != bj;
             st.timed = st.timed && hipEventRecord(st.ev1, c->stream) == hipSuccess;
             if (!st.timed)
                 (void)hipStreamSynchronize(c->stream);
             st.in_flight = true;
+            if (!s->p.overlap)
+                finish_step(s, st);
         }
         // The previous step ends while this one waits behind it on the device.
         finish_step(s, prev);
@@ -463,7 +468,7 @@ int sieve_server_create(sieve_ctx *ctx, const sieve_server_params *p, sieve_serv
     if (!q.step_tiles)
         q.step_tiles = 16u * (uint32_t)ctx->cus;
     if (!q.quantum_tiles)
-        q.quantum_tiles = std::max<uint32_t>(1, q.step_tiles / 8);
+        q.quantum_tiles = std::max<uint32_t>(1, q.step_tiles / 16);
     if (!q.elem_bytes)
         q.elem_bytes = 8;
     if (!q.max_queue)

@@ -28,7 +28,8 @@ from paper_2310_17746_amd import workloads  # noqa: E402
 LAMBDA = 4.0e4  # arrivals per second (about 0.8 of the measured saturated rate)
 
 
-def test_serving_mix_full_shape(pi_table):
+@pytest.mark.parametrize("overlap", [0, 1])
+def test_serving_mix_full_shape(pi_table, overlap):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     lo, hi, mode, gaps = workloads.serving_requests(1)
@@ -44,7 +45,7 @@ def test_serving_mix_full_shape(pi_table):
         digests = {}
         done = {}
         pool = ThreadPoolExecutor(16)
-        with pkg.Server(s, out_budget_bytes=64 << 30, elem_bytes=8) as srv:
+        with pkg.Server(s, out_budget_bytes=64 << 30, elem_bytes=8, overlap=overlap) as srv:
             t0 = srv.now_ns() + 2_000_000
             srv.submit(long_lo, long_hi, 0, n, at_ns=t0)
             arrivals = np.cumsum(gaps) / LAMBDA * 1e9

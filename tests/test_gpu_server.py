@@ -39,7 +39,8 @@ def _drain(srv, n, timeout_s=120):
     return got
 
 
-def test_alone_vs_mix_with_long_job(sv):
+@pytest.mark.parametrize("overlap", [0, 1])
+def test_alone_vs_mix_with_long_job(sv, overlap):
     pi = {int(x): int(v) for x, v in read_golden("pi_values.txt")}
     rng = np.random.default_rng(5)
     n = 120
@@ -51,7 +52,7 @@ def test_alone_vs_mix_with_long_job(sv):
     alone_c = [sv.count(int(a), int(b)) for a, b in zip(lo, hi)]
     alone_l = {i: _u(sv.list(int(lo[i]), int(hi[i]), elem_bytes=8)) for i in range(n) if mode[i]}
     long_tag = 10 ** 6
-    with pkg.Server(sv, out_budget_bytes=512 << 20, step_tiles=96, quantum_tiles=4) as srv:
+    with pkg.Server(sv, out_budget_bytes=512 << 20, step_tiles=96, quantum_tiles=4, overlap=overlap) as srv:
         srv.submit(2, 10 ** 10 + 1, 0, long_tag)
         for i in range(n):
             srv.submit(int(lo[i]), int(hi[i]), int(mode[i]), i)
@@ -70,10 +71,13 @@ def test_alone_vs_mix_with_long_job(sv):
         assert np.mean(short_done < got[long_tag]["t_done_ns"]) > 0.9
         st = srv.stats()
         assert st["completed"] == n + 1 and st["active"] == 0
+        assert (st["overlap_steps"] > 0) == bool(overlap)
+        assert 0 < st["busy_ns"] <= st["elapsed_ns"]
 
 
-def test_cancel_long_job(sv):
-    with pkg.Server(sv, step_tiles=32, quantum_tiles=2) as srv:
+@pytest.mark.parametrize("overlap", [0, 1])
+def test_cancel_long_job(sv, overlap):
+    with pkg.Server(sv, step_tiles=32, quantum_tiles=2, overlap=overlap) as srv:
         srv.submit(2, 10 ** 11 + 1, 0, 7)
         time.sleep(0.05)
         assert srv.cancel(7) == 0
