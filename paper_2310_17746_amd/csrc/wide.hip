@@ -11,19 +11,21 @@
 //     first multiples at or past W, or P*P when that lies past W (Sec. 2.4);
 //   * the presieve phases (W / 6) mod period of the pattern groups;
 //   * the output, W + offset as 128-bit values.
-// lo >= 2^40 keeps every prime marked in LDS (at most one tile's plane
-// length, below 2^20) below the square root of W, so those need no square
-// test, and keeps 1, 2, 3 and the presieved primes out of every window.
+// lo >= 2^40 keeps every prime marked in LDS (at most 16 plane lengths,
+// below 2^24) below W, so the first multiple at or past W is never the prime
+// itself; those primes start there with no square test (from W instead of
+// P * P they only mark composites twice).  It also keeps 1, 2, 3 and the
+// presieved primes out of every window.
 //
 // Work split by prime size:
 //   * 5..73: the presieve pattern tables, which initialise each tile's planes;
-//   * up to one tile's plane length: LDS marks tile by tile, each start from
-//     the window residue plus the tile's offset (one 64-by-32-bit reduction);
+//   * up to 16 plane lengths: LDS marks tile by tile, each start from the
+//     window residue plus the tile's offset (one 64-by-32-bit reduction);
 //     the smallest of them split over several lanes as in the 64-bit path;
-//   * the rest (at most one hit per plane per tile), resident primes below
-//     2^32 and the 64-bit extension primes: one thread per prime walks all
-//     of its multiples in the window and sets them in the window's bitmap in
-//     HBM with 64-bit atomic ORs.
+//   * the rest (a hit per plane every 16 tiles or fewer), resident primes
+//     below 2^32 and the 64-bit extension primes: one thread per prime walks
+//     all of its multiples in the window and sets them in the window's
+//     bitmap in HBM with 64-bit atomic ORs.
 // Each tile then merges its planes with the bitmap words, keeps the values of
 // [lo, hi) that no prime marked, writes them back as prime bits (lists) and
 // counts them per chunk.
@@ -51,6 +53,7 @@ constexpr uint32_t kWideThreads = 1024;      // tile kernel
 constexpr uint32_t kLargeThreads = 256;      // large-prime kernel
 constexpr uint32_t kMaxTileChunks = 64;      // bitmap chunks per tile (pw <= 32768)
 constexpr uint64_t kExtSample = 4096;        // extension primes per host sample
+constexpr uint64_t kMidPlanes = 16;          // LDS-marked primes: up to this many plane lengths
 
 struct WideArgs {
     uint64_t wlo, whi;          // W, the window base (a multiple of 6)
@@ -403,7 +406,14 @@ int wide_job(sieve_ctx *c, const sieve_u128 &lo128, const sieve_u128 &hi128, boo
         if (st != SIEVE_OK)
             return st;
     }
-    const uint64_t mid_top = std::min<uint64_t>(root, 32ull * pw);
+    // Primes up to kMidPlanes plane lengths take a Table 1 start per tile in
+    // LDS, larger ones walk the window with atomic ORs: measured, a start
+    // costs about a sixteenth of an atomic OR to HBM, so the break-even lies
+    // near 16 plane lengths (one hit per prime per 16 tiles).  A window of
+    // few tiles keeps most CUs out of the tile kernel, so there the cut-off
+    // shrinks with the tiles per CU.
+    const uint64_t planes = std::max<uint64_t>(1, std::min<uint64_t>(kMidPlanes, kMidPlanes * nt / c->cus));
+    const uint64_t mid_top = std::min<uint64_t>(root, planes * 32ull * pw);
     const uint32_t n_mid = rt::primes_upto(c, mid_top);
     const uint64_t nwords = (nt - 1) * pw + last_words;
     const uint64_t nch = (nt - 1) * (pw / kChunkWords) + (last_words + kChunkWords - 1) / kChunkWords;
