@@ -37,6 +37,8 @@ host threads) timed on a bounded slice of the same workload.
 * serve_2000: 2000 seeded requests with Poisson arrivals at 0.8 x the
   saturated request rate (measured first with all requests at t = 0) and the
   count of [2, 10^12] submitted at t = 0; p50/p99 of completion - arrival.
+* wide: windows past 2^64 (128-bit values): the count of
+  [2^64, 2^64 + 10^10) and the list of [2^64, 2^64 + 10^9).
 """
 from __future__ import annotations
 
@@ -121,9 +123,9 @@ def kernel_sources_sha() -> str:
 
 
 def measured_traffic(params):
-    """Counter figures per k_sieve dispatch from the committed summary, if it
-    was taken on the current kernel sources with the same launch shape (else
-    None)."""
+    """Counter figures per k_sieve dispatch from the committed summary: the
+    entry taken with the same launch shape, if the summary was taken on the
+    current kernel sources (else None)."""
     path = os.path.join(ROOT, "profiles", "k_sieve_pi1e11_traffic.json")
     try:
         with open(path) as f:
@@ -133,9 +135,10 @@ def measured_traffic(params):
     if t.get("kernel_sources_sha256") != kernel_sources_sha():
         return None
     shape = ("segment_bytes", "block_threads", "wg_per_cu", "strip_tiles")
-    if any(t.get("params", {}).get(k) != params.get(k) for k in shape):
-        return None
-    return t
+    for e in t.get("entries", []):
+        if all(e.get("params", {}).get(k) == params.get(k) for k in shape):
+            return e
+    return None
 
 
 def bench_list(pkg, torch, params, steps=5):
@@ -367,6 +370,38 @@ def bench_serve(pkg, workloads):
             "steps": st["steps"], "overlap_steps": st["overlap_steps"]}
 
 
+def bench_wide(pkg, torch, params, steps=3):
+    """Windows past 2^64 (128-bit values): the count of [2^64, 2^64 + 10^10)
+    and the list of [2^64, 2^64 + 10^9), with the base primes below 2^32
+    resident and the extension list reaching isqrt(2^64 + 10^10)."""
+    T64 = 1 << 64
+    s = pkg.Sieve(0, params)
+    t0 = time.perf_counter()
+    s.base_primes((1 << 32) - 1)
+    clo, chi = T64, T64 + 10 ** 10
+    s.ensure_base_wide_for(chi)
+    base_s = time.perf_counter() - t0
+    n = s.count_wide(clo, chi)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        s.count_wide(clo, chi)
+    dt_c = (time.perf_counter() - t1) / steps
+    llo, lhi = T64, T64 + 10 ** 9
+    out = torch.empty((pkg.list_bound_wide(llo, lhi), 2), dtype=torch.int64, device="cuda")
+    m = s.list_wide(llo, lhi, out=out).shape[0]
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(steps):
+        s.list_wide(llo, lhi, out=out)
+    dt_l = (time.perf_counter() - t2) / steps
+    s.close()
+    return {"workload": "count of [2^64, 2^64 + 10^10) and 128-bit list of [2^64, 2^64 + 10^9)",
+            "count": n, "count_ms": round(dt_c * 1e3, 3), "count_ints_per_s": round((chi - clo) / dt_c, 1),
+            "listed": m, "list_ms": round(dt_l * 1e3, 3), "list_ints_per_s": round((lhi - llo) / dt_l, 1),
+            "base_primes_s": round(base_s, 2)}
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -451,7 +486,8 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true", help="headline count only")
     ap.add_argument("--cpu-sample", type=int, default=10 ** 11,
                     help="integers of the oracle's timed slice (the top of the range)")
-    ap.add_argument("--extra", default="", choices=["", "list_1e9", "list_window", "batch_4096", "serve_2000"],
+    ap.add_argument("--extra", default="",
+                    choices=["", "list_1e9", "list_window", "batch_4096", "serve_2000", "wide"],
                     help="run only this extra workload and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (5 times), the reference "
@@ -489,7 +525,8 @@ def main() -> int:
         fn = {"list_1e9": lambda: bench_list(pkg, torch, params),
               "list_window": lambda: bench_list_window(pkg, torch, params),
               "batch_4096": lambda: bench_batch(pkg, torch, params, workloads),
-              "serve_2000": lambda: bench_serve(pkg, workloads)}[args.extra]
+              "serve_2000": lambda: bench_serve(pkg, workloads),
+              "wide": lambda: bench_wide(pkg, torch, params)}[args.extra]
         print(json.dumps({"extra": args.extra, **fn()}), flush=True)
         return 0
     # Launch shape of the headline count: the autotuner's pick for this very
@@ -576,7 +613,8 @@ def main() -> int:
                          ("list_window", lambda: bench_list_window(pkg, torch, params)),
                          ("batch_4096", lambda: bench_batch(pkg, torch, bparams, workloads)),
                          ("stream", lambda: bench_stream(pkg, torch, params)),
-                         ("serve_2000", lambda: bench_serve(pkg, workloads))):
+                         ("serve_2000", lambda: bench_serve(pkg, workloads)),
+                         ("wide", lambda: bench_wide(pkg, torch, params))):
             print("bench: %s" % name, file=sys.stderr, flush=True)
             extras[name] = fn()
         extras["batch_4096"]["autotune"] = {"chosen": tuned["params"], "sample_ms": round(tuned["ms"], 3),
