@@ -145,3 +145,50 @@ def test_extension_primes_past_2_66(sv):
         v += (1 - v % 6) % 6
         if v < hi:
             assert (v in vals) == brute.is_prime_mr(v), v
+
+
+def test_wide_list_at_bench_size(sv):
+    """The bench's wide list, [2^64, 2^64 + 10^9) at the default launch shape:
+    sorted, in range, on the wheel; the oracle's list on sampled sub-windows
+    and across sampled tile seams; Miller-Rabin on sampled members and
+    non-members; the count equals the list length and the sum of the counts
+    of ten pieces."""
+    lo, hi = T64, T64 + 10 ** 9
+    print("wide: bench-size list [%d, %d)" % (lo, hi), flush=True)
+    g = sv.list_wide(lo, hi).cpu().numpy().view(np.uint64).reshape(-1, 2)
+    assert np.all(g[:, 1] == 1)  # every value in [2^64, 2^65)
+    low = g[:, 0]
+    assert np.all(low[1:] > low[:-1])
+    assert int(low[-1]) < hi - T64 and int(low[0]) >= 0
+    r6 = (low + np.uint64(T64 % 6)) % np.uint64(6)
+    assert set(np.unique(r6).tolist()) <= {1, 5}
+    n = len(low)
+    assert sv.count_wide(lo, hi) == n
+    step = 10 ** 8
+    assert sum(sv.count_wide(lo + k * step, lo + (k + 1) * step) for k in range(10)) == n
+    # sub-windows: random offsets, the first and last tile seams and six
+    # random ones (tiles of 192 * pw integers)
+    pw = sv.params.segment_bytes // 8
+    span = 192 * pw
+    nseam = (hi - lo) // span
+    rng = np.random.default_rng(11)
+    offs = [int(x) for x in rng.integers(0, hi - lo - 10 ** 6, 4)]
+    offs += [k * span - 50000 for k in [1, nseam] + [int(x) for x in rng.integers(2, nseam, 6)]]
+    for o in offs:
+        a, b = lo + max(o, 0), min(lo + max(o, 0) + 10 ** 5, hi)
+        want = oracle.primes_wide(a, b)
+        sel = (low >= np.uint64(a - T64)) & (low < np.uint64(b - T64))
+        got = low[sel]
+        assert np.array_equal(got, want[:, 0]) and np.all(want[:, 1] == 1), (a, b)
+    members = set(int(x) for x in low[rng.integers(0, n, 100)])
+    for v in members:
+        assert brute.is_prime_mr(T64 + v)
+    cand = 0
+    while cand < 100:
+        v = int(rng.integers(0, hi - lo))
+        v += (1 - (T64 + v) % 6) % 6
+        if v < hi - lo:
+            cand += 1
+            k = int(np.searchsorted(low, np.uint64(v)))
+            assert (k < n and int(low[k]) == v) == brute.is_prime_mr(T64 + v), v
+
