@@ -280,9 +280,10 @@ int sieve_count_batch_static(sieve_ctx *ctx, const uint64_t *lo, const uint64_t 
  * when that lies past W (Sec. 2.4), and the survivors are counted or listed
  * as W + offset.  Base primes: every prime below 2^32 resident plus an
  * extension list of 64-bit primes from 2^32 up to the extension limit; a
- * window needs isqrt(hi - 1) within them, else SIEVE_E_RANGE.  These calls
- * wait for the context's earlier stream-ordered jobs, run on `stream` (NULL:
- * the context stream) and return when done.
+ * window needs isqrt(hi - 1) within them, else SIEVE_E_RANGE.  A window
+ * whose bucket entries would exceed bucket_mem_mb runs as equal pieces of
+ * whole tiles.  These calls wait for the context's earlier stream-ordered
+ * jobs, run on `stream` (NULL: the context stream) and return when done.
  */
 typedef struct sieve_u128 {
     uint64_t lo, hi;

@@ -862,8 +862,48 @@ __device__ inline void walk_step(uint32_t &t, uint32_t &b, uint32_t &c, const Hi
     c = c == 4 ? 0 : (c == 5 ? 5 : c + 1);
 }
 
+// Wide windows: the first hits of prime P (below 2^32) in plane order at or
+// past the window offset x0 (a multiple of 6; the value W + x0), as indices
+// from x0, and that value mod 5.  With P * P at or before W + x0 the first
+// value is W + x0 itself: rem = (W + x0 - 1) mod P from the 128-bit W - 1 by
+// 32-bit limbs, and Table 1 in 64-bit arithmetic (the packed R of a prime
+// above 3.2e9 and the 32-bit start formula do not hold there).  Otherwise
+// P * P lies in the window at offset x2 = P * P - W: its A_one index from x0
+// is (x2 - x0 - 1) / 6 and A_five follows by P (P + 4) or P (P + 2).
+__device__ inline bool wide_first_hits(const BucketArgs &a, uint32_t P, uint64_t m, uint64_t x0, uint64_t xend,
+                                       uint64_t &id1, uint64_t &id5)
+{
+    const uint64_t P2 = (uint64_t)P * P;
+    const uint64_t blo = a.wlo + x0;
+    const uint64_t bhi = a.whi + (blo < x0 ? 1u : 0u);  // W + x0, 128-bit
+    if (bhi != 0 || P2 <= blo) {
+        uint64_t r = mod_invariant(a.wm1_hi, P, m, false);
+        r = mod_invariant((r << 32) | (a.wm1_lo >> 32), P, m, false);
+        r = mod_invariant((r << 32) | (a.wm1_lo & 0xFFFFFFFFull), P, m, false);
+        r += mod_invariant(x0, P, m, false);
+        const uint64_t rem = r >= P ? r - P : r;  // (W + x0 - 1) mod P
+        const uint64_t R = P / 6u;
+        const bool p5 = P - 6u * (uint32_t)R == 5u;
+        const uint64_t dp = 6 * R + 5 - rem;
+        const uint64_t i0 = dp / 6;
+        const uint32_t q = (uint32_t)(dp - 6 * i0);
+        const uint32_t e1 = (uint32_t)((p5 ? kTable1_id1_p5 : kTable1_id1_p1) >> (8u * q));
+        const uint32_t e5 = (uint32_t)((p5 ? kTable1_id5_p5 : kTable1_id5_p1) >> (8u * q));
+        id1 = i0 + (e1 & 7u) * R + ((e1 >> 3) & 7u) - 1u;
+        id5 = i0 + (e5 & 7u) * R + ((e5 >> 3) & 7u) - 1u;
+        return true;
+    }
+    const uint64_t x2 = P2 - a.wlo;  // P * P - W, with W below 2^64 here
+    if (x2 >= xend)
+        return false;
+    id1 = (x2 - x0 - 1) / 6;
+    id5 = id1 + (P % 6u == 1u ? 2ull * (P - 1) / 3 : (P - 2ull) / 3);
+    return true;
+}
+
 // First hits of prime k in tiles [w0, wend) of range d (tile indices
 // relative to the range's tile 0; t = wend when there is none).
+template <bool WIDE>
 __device__ inline HitWalk walk_init(const BucketArgs &a, const RangeDesc &d, uint32_t k, uint32_t w0,
                                     uint32_t wend)
 {
@@ -874,6 +914,29 @@ __device__ inline HitWalk walk_init(const BucketArgs &a, const RangeDesc &d, uin
     w.c1 = w.c5 = 5;
     if (k >= d.nact)
         return w;
+    if constexpr (WIDE) {
+        const PrimeConst pc = a.prm[k];
+        const uint32_t P = pc.p;
+        const uint64_t x0 = (uint64_t)w0 * a.span, xend = (uint64_t)wend * a.span;
+        uint64_t id1, id5;
+        if (!wide_first_hits(a, P, prime_recip(pc), x0, xend, id1, id5))
+            return w;
+        // tiles from w0 (the square case's indices count from x0 as well)
+        if (a.skip5) {
+            const uint32_t b5 = (uint32_t)((a.w5 + x0 % 5u) % 5u);
+            const uint32_t inv5 = inv_mod5(P % 5u);
+            w.c1 = ((b5 + (uint32_t)(id1 % 5u) + 1u) * inv5) % 5u;
+            w.c5 = ((b5 + (uint32_t)(id5 % 5u)) * inv5) % 5u;
+        }
+        w.qp = P / a.nbits;
+        w.rp = P - w.qp * a.nbits;
+        const uint64_t t1 = w0 + id1 / a.nbits, t5 = w0 + id5 / a.nbits;
+        w.t1 = t1 < wend ? (uint32_t)t1 : wend;
+        w.b1 = (uint32_t)(id1 % a.nbits);
+        w.t5 = t5 < wend ? (uint32_t)t5 : wend;
+        w.b5 = (uint32_t)(id5 % a.nbits);
+        return w;
+    }
     const PrimeConst pc = a.prm[k];
     const uint64_t P = pc.p;
     const uint64_t P2 = P * P;
@@ -950,7 +1013,7 @@ __device__ inline uint32_t find_unit_range(const RangeDesc *ranges, uint32_t nra
 // walking again when the thread had no more hits than that.
 static_assert(kBucketWindow <= (1u << 11), "kept hits hold the window tile in 11 bits");
 
-template <int PASS>
+template <int PASS, bool WIDE>
 __global__ void __launch_bounds__(kBucketThreads) k_bucket(BucketArgs a)
 {
     extern __shared__ unsigned long long s_bucket[];
@@ -977,7 +1040,7 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket(BucketArgs a)
         const uint32_t w0 = win * kBucketWindow;
         const uint32_t wend = (d.ntiles - w0) < kBucketWindow ? d.ntiles : w0 + kBucketWindow;
         const uint32_t k = d.kbig + blk * kBucketThreads + tid;
-        HitWalk w = walk_init(a, d, k, w0, wend);
+        HitWalk w = walk_init<WIDE>(a, d, k, w0, wend);
 #ifdef SIEVE_MARK_COUNT
         // hits past the range's last plane word are binned but never applied
         const uint32_t lastbits = 32u * d.last_words;
@@ -1541,7 +1604,7 @@ template <int PASS>
 int bucket_residency(size_t lds)
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bucket<PASS>, kBucketThreads, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bucket<PASS, false>, kBucketThreads, lds) != hipSuccess ||
         nb < 1) {
         (void)hipGetLastError();
         nb = 1;
@@ -1569,12 +1632,21 @@ hipError_t launch_bucket(const BucketArgs &a, int pass, uint32_t cus, hipStream_
         occ[pass][w2].store(nb, std::memory_order_relaxed);
     }
     const dim3 grid(cus * (uint32_t)nb);
-    if (pass == 0)
-        hipLaunchKernelGGL(k_bucket<0>, grid, dim3(kBucketThreads), lds, s, a);
-    else if (pass == 1)
-        hipLaunchKernelGGL(k_bucket<1>, grid, dim3(kBucketThreads), lds, s, a);
-    else
-        hipLaunchKernelGGL(k_bucket<2>, grid, dim3(kBucketThreads), lds, s, a);
+    if (a.wide) {
+        // windows past 64 bits: the exact layout only
+        if (pass == 0)
+            hipLaunchKernelGGL((k_bucket<0, true>), grid, dim3(kBucketThreads), lds, s, a);
+        else if (pass == 1)
+            hipLaunchKernelGGL((k_bucket<1, true>), grid, dim3(kBucketThreads), lds, s, a);
+        else
+            return hipErrorInvalidValue;
+    } else if (pass == 0) {
+        hipLaunchKernelGGL((k_bucket<0, false>), grid, dim3(kBucketThreads), lds, s, a);
+    } else if (pass == 1) {
+        hipLaunchKernelGGL((k_bucket<1, false>), grid, dim3(kBucketThreads), lds, s, a);
+    } else {
+        hipLaunchKernelGGL((k_bucket<2, false>), grid, dim3(kBucketThreads), lds, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -166,6 +166,11 @@ struct BucketArgs {
     uint32_t win;                 // LDS bins per workgroup: >= the tiles of every unit's window
     uint32_t pad;
     unsigned long long *tally;    // debug build only, as in SieveArgs
+    // A window past 64 bits (range values are offsets from its base W):
+    uint32_t wide;                // 1: starts from (W - 1) mod P, 64-bit Table 1
+    uint32_t w5;                  // W mod 5
+    uint64_t wlo, whi;            // W
+    uint64_t wm1_lo, wm1_hi;      // W - 1
 };
 
 struct BucketScanArgs {

@@ -22,10 +22,15 @@
 //   * up to 16 plane lengths: LDS marks tile by tile, each start from the
 //     window residue plus the tile's offset (one 64-by-32-bit reduction);
 //     the smallest of them split over several lanes as in the 64-bit path;
-//   * the rest (a hit per plane every 16 tiles or fewer), resident primes
-//     below 2^32 and the 64-bit extension primes: one thread per prime walks
-//     all of its multiples in the window and sets them in the window's
-//     bitmap in HBM with 64-bit atomic ORs.
+//   * the next resident primes, with at least two hits in the window (P
+//     below a plane's bits over the whole window): the bucket sieve of the
+//     64-bit path in its exact layout, its walks started from the window
+//     residue, and each tile ORs its entries into LDS;
+//   * the sparse rest, resident primes below 2^32 and the 64-bit extension
+//     primes: one thread per prime walks its few multiples in the window
+//     and sets them in the window's bitmap in HBM with 64-bit atomic ORs (a
+//     bucket walk costs each prime two passes of setup, which pays off only
+//     from about two hits on).
 // Each tile then merges its planes with the bitmap words, keeps the values of
 // [lo, hi) that no prime marked, writes them back as prime bits (lists) and
 // counts them per chunk.
@@ -45,6 +50,10 @@ namespace sieve {
 hipError_t launch_finalize(const FinalizeArgs &a, uint32_t grid, hipStream_t s);
 hipError_t launch_seg(const SegArgs &a, int pass, uint32_t grid, hipStream_t s);
 hipError_t launch_compact_wide(const CompactArgs &a, uint32_t grid, hipStream_t s);
+hipError_t launch_zero(const JobHeader *job, unsigned long long *counters, unsigned long long *counts,
+                       uint32_t *bcount, uint32_t *gbm, uint32_t *garrive, unsigned long long *tally, hipStream_t s);
+hipError_t launch_bucket(const BucketArgs &a, int pass, uint32_t cus, hipStream_t s);
+hipError_t launch_bucket_scan(const BucketScanArgs &a, hipStream_t s);
 
 namespace {
 
@@ -69,9 +78,12 @@ struct WideArgs {
     uint32_t k_split;           // primes [first_mark, k_split) are split into items
     uint32_t n_mid;             // primes [first_mark, n_mid) are marked in LDS
     uint32_t n_act;             // resident primes with P * P < hi
+    uint32_t k_atomic;          // resident primes [k_atomic, n_act) walk the window with atomics
     const uint32_t *wr;         // (W - 1) mod P by prime index, for indices < n_mid
     const uint64_t *ext;        // extension primes with P * P < hi
     uint64_t n_ext;
+    const uint32_t *bdata;      // bucket entries of the resident large primes (bit | plane << 31),
+    const unsigned long long *boff;  // tile t's at [boff[t], boff[t + 1]); NULL: no buckets
     const uint2 *ps_tab;
     PsGroup groups[kMaxGroups];
     uint32_t wphase[kMaxGroups];  // (W / 6) mod period
@@ -167,19 +179,20 @@ __global__ void k_wide_prep(WideArgs a, uint32_t *wr)
     }
 }
 
-// Primes beyond one tile's plane length: every multiple in the window, ORed
+// Primes with a few hits in the whole window at most (resident ones from
+// k_atomic on, then the extension list): every multiple in the window, ORed
 // into the bitmap (bit 2i: A_one index i, bit 2i + 1: A_five index i, of
 // word i / 32).  Marks past hi are dropped by the tile kernel's range mask.
 __global__ void __launch_bounds__(kLargeThreads) k_wide_large(WideArgs a)
 {
-    const uint64_t nres = a.n_act > a.n_mid ? a.n_act - a.n_mid : 0;
+    const uint64_t nres = a.n_act > a.k_atomic ? a.n_act - a.k_atomic : 0;
     const uint64_t n = nres + a.n_ext;
     const uint64_t nbits = 32ull * a.nwords;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
         uint64_t P, rem;
         if (j < nres) {
-            const PrimeConst pc = a.prm[a.n_mid + j];
+            const PrimeConst pc = a.prm[a.k_atomic + j];
             P = pc.p;
             rem = mod128_small(a.wm1_hi, a.wm1_lo, pc.p, prime_recip(pc));
         } else {
@@ -302,9 +315,21 @@ __global__ void __launch_bounds__(kWideThreads) k_wide_tile(WideArgs a)
                     atomicOr(&pl5[i >> 5], 1u << (i & 31));
             }
         }
+
+        // Bucket entries of the resident large primes (entries past the
+        // last tile's words are dropped).
+        if (a.boff) {
+            const unsigned long long e0 = a.boff[t], e1 = a.boff[t + 1];
+            for (unsigned long long e = e0 + tid; e < e1; e += kWideThreads) {
+                const uint32_t v = a.bdata[e];
+                const uint32_t bit = v & 0x7FFFFFFFu;
+                if (bit < nb)
+                    atomicOr(&(v >> 31 ? pl5 : pl1)[bit >> 5], 1u << (bit & 31));
+            }
+        }
         __syncthreads();
 
-        // Merge with the large primes' marks, keep [lo, hi), count per chunk.
+        // Merge with the extension primes' marks, keep [lo, hi), count per chunk.
         // The loop bound is uniform so that every lane takes part in the
         // wave sums; 64 consecutive words lie in one chunk.
         for (uint32_t w0 = 0; w0 < nw; w0 += kWideThreads) {
@@ -372,14 +397,49 @@ int ext_upto(sieve_ctx *c, uint64_t x, uint64_t &n)
     return SIEVE_OK;
 }
 
-// One wide window: count (out == NULL and !list) or list into out.
-int wide_job(sieve_ctx *c, const sieve_u128 &lo128, const sieve_u128 &hi128, bool list, U128 *out, uint64_t cap,
-             uint64_t *count, hipStream_t stream)
+// Base primes of a window ending at H: resident ones up to isqrt(H - 1)
+// (n_act) and extension ones (n_ext).  The resident store ends below 2^32;
+// 2^32 itself is not prime, so the extension list is needed from
+// isqrt(H - 1) = 2^32 + 1 on.
+int window_primes(sieve_ctx *c, u128 H, uint64_t &root, uint32_t &n_act, uint64_t &n_ext)
 {
-    const u128 L = to_u128(lo128), H = to_u128(hi128);
-    if (L < (u128)SIEVE_WIDE_MIN_LO || H < L || H - L > (u128)SIEVE_WIDE_MAX_SPAN)
-        return SIEVE_E_INVAL;
-    *count = 0;
+    root = isqrt_u128(H - 1);
+    constexpr uint64_t kResTop = 0xFFFFFFFFull;
+    const uint64_t res_need = std::min<uint64_t>(root, kResTop);
+    const bool need_ext = root > kResTop + 1;
+    if (c->limit < res_need || (need_ext && c->ext_limit < root))
+        return SIEVE_E_RANGE;
+    n_act = rt::primes_upto(c, res_need);
+    n_ext = 0;
+    return need_ext ? ext_upto(c, root, n_ext) : SIEVE_OK;
+}
+
+// Resident primes marked in LDS tile by tile: up to kMidPlanes plane lengths.
+// Measured, a start costs about a sixteenth of an atomic OR to HBM, so the
+// break-even of per-tile starts lies near 16 plane lengths (one hit per prime
+// per 16 tiles).  A window of few tiles keeps most CUs out of the tile
+// kernel, so there the cut-off shrinks with the tiles per CU.
+uint32_t mid_primes(const sieve_ctx *c, uint64_t root, uint64_t nt)
+{
+    const uint32_t pw = c->prm.segment_bytes / 8;
+    const uint64_t planes = std::max<uint64_t>(1, std::min<uint64_t>(kMidPlanes, kMidPlanes * nt / c->cus));
+    return std::max(rt::primes_upto(c, std::min<uint64_t>(root, planes * 32ull * pw)), c->first_mark);
+}
+
+// End of the bucketed resident primes for a window of nwords plane words:
+// primes below its plane bits, which hit it at least twice (measured: a
+// cut-off at 1, 2, 4 or 8 hits gives 26.3, 24.6, 25.6 and 27.8 ms for the
+// count of [2^64, 2^64 + 10^10)).
+uint32_t bucket_end(const sieve_ctx *c, uint64_t root, uint64_t nwords)
+{
+    const uint64_t top = std::min<uint64_t>(std::min<uint64_t>(root, 0xFFFFFFFFull), 32ull * nwords);
+    return top > c->limit ? (uint32_t)c->h_primes.size() : rt::primes_upto(c, top);
+}
+
+// One window piece [L, H) (validated by the caller): count, or list into out.
+int wide_piece(sieve_ctx *c, u128 L, u128 H, bool list, U128 *out, uint64_t cap, uint64_t &count, hipStream_t s)
+{
+    count = 0;
     const u128 W = L - L % 6;
     const uint64_t lo_rel = (uint64_t)(L - W), hi_rel = (uint64_t)(H - W);
     const uint32_t pw = c->prm.segment_bytes / 8;
@@ -390,45 +450,23 @@ int wide_job(sieve_ctx *c, const sieve_u128 &lo128, const sieve_u128 &hi128, boo
         return SIEVE_OK;
     if (nt > 0xFFFFFFFFull || pw > kMaxTileChunks * kChunkWords)
         return SIEVE_E_INVAL;
-    // Base primes: every prime <= isqrt(hi - 1).
-    const uint64_t root = isqrt_u128(H - 1);
-    // The resident store ends below 2^32; 2^32 itself is not prime, so the
-    // extension list is needed from root = 2^32 + 1 on.
-    constexpr uint64_t kResTop = 0xFFFFFFFFull;
-    const uint64_t res_need = std::min<uint64_t>(root, kResTop);
-    const bool need_ext = root > kResTop + 1;
-    if (c->limit < res_need || (need_ext && c->ext_limit < root))
-        return SIEVE_E_RANGE;
-    const uint32_t n_act = rt::primes_upto(c, res_need);
-    uint64_t n_ext = 0;
-    if (need_ext) {
-        const int st = ext_upto(c, root, n_ext);
-        if (st != SIEVE_OK)
-            return st;
-    }
-    // Primes up to kMidPlanes plane lengths take a Table 1 start per tile in
-    // LDS, larger ones walk the window with atomic ORs: measured, a start
-    // costs about a sixteenth of an atomic OR to HBM, so the break-even lies
-    // near 16 plane lengths (one hit per prime per 16 tiles).  A window of
-    // few tiles keeps most CUs out of the tile kernel, so there the cut-off
-    // shrinks with the tiles per CU.
-    const uint64_t planes = std::max<uint64_t>(1, std::min<uint64_t>(kMidPlanes, kMidPlanes * nt / c->cus));
-    const uint64_t mid_top = std::min<uint64_t>(root, planes * 32ull * pw);
-    const uint32_t n_mid = rt::primes_upto(c, mid_top);
+    uint64_t root, n_ext;
+    uint32_t n_act;
+    int st = window_primes(c, H, root, n_act, n_ext);
+    if (st != SIEVE_OK)
+        return st;
+    const uint32_t n_mid = std::min(mid_primes(c, root, nt), std::max(n_act, c->first_mark));
+    const uint64_t nwords_all = (nt - 1) * pw + last_words;
+    const uint32_t n_big = std::max(n_mid, bucket_end(c, root, nwords_all));
+    const bool buckets = n_big > n_mid;  // resident primes bucketed past the LDS-marked ones
     const uint64_t nwords = (nt - 1) * pw + last_words;
     const uint64_t nch = (nt - 1) * (pw / kChunkWords) + (last_words + kChunkWords - 1) / kChunkWords;
     const uint64_t nseg = (nch + kSegChunks - 1) / kSegChunks;
-    int st = rt::ensure_capacity(c, 1, nch, nt, 0);
+    st = rt::ensure_capacity(c, 1, nch, nt, 0);
     if (st != SIEVE_OK)
         return st;
     if (!c->d_wr.reserve(std::max<uint32_t>(n_mid, 1)))
         return SIEVE_E_NOMEM;
-    hipStream_t s = stream ? stream : c->stream;
-    // The scratch is shared with the context's stream-ordered jobs.
-    if (c->last_valid && hipEventSynchronize(c->last_ev) != hipSuccess) {
-        (void)hipGetLastError();
-        return SIEVE_E_DEVICE;
-    }
 
     WideArgs a;
     memset(&a, 0, sizeof a);
@@ -448,8 +486,9 @@ int wide_job(sieve_ctx *c, const sieve_u128 &lo128, const sieve_u128 &hi128, boo
     a.item_prefix = c->d_item_prefix.p;
     a.first_mark = c->first_mark;
     a.k_split = c->k_split;
-    a.n_mid = std::max(n_mid, c->first_mark);
-    a.n_act = std::max(n_act, a.n_mid);
+    a.n_mid = n_mid;
+    a.n_act = std::max(n_act, n_big);
+    a.k_atomic = n_big;
     a.wr = c->d_wr.p;
     a.ext = c->d_ext.p;
     a.n_ext = n_ext;
@@ -464,8 +503,8 @@ int wide_job(sieve_ctx *c, const sieve_u128 &lo128, const sieve_u128 &hi128, boo
     a.chunk_counts = c->d_chunk_counts.p;
     a.counts = c->d_counts.p;
 
-    // Job blob for the shared finalize / scan / compaction kernels: one
-    // range in offsets from W.
+    // Job blob for the shared bucket / finalize / scan / compaction kernels:
+    // one range in offsets from W.
     JobHeader h;
     memset(&h, 0, sizeof h);
     RangeDesc d;
@@ -476,6 +515,10 @@ int wide_job(sieve_ctx *c, const sieve_u128 &lo128, const sieve_u128 &hi128, boo
     d.ntiles = (uint32_t)nt;
     d.last_words = last_words;
     d.mode = list ? 1u : 0u;
+    d.nact = n_big;  // the bucket sieve takes primes [kbig, nact)
+    d.kbig = n_mid;
+    d.bwins = (uint32_t)((nt + kBucketWindow - 1) / kBucketWindow);
+    d.bunits = buckets ? ((n_big - n_mid + kBucketThreads - 1) / kBucketThreads) * d.bwins : 0;
     if (list) {
         d.nchunks = (uint32_t)nch;
         d.nseg = (uint32_t)nseg;
@@ -487,12 +530,16 @@ int wide_job(sieve_ctx *c, const sieve_u128 &lo128, const sieve_u128 &hi128, boo
     h.ntiles = nt;
     h.nchunks = list ? nch : 0;
     h.nseg = list ? nseg : 0;
+    h.nunits = d.bunits;
+    h.bmode = 2;
     h.nranges = 1;
     h.nlist = list ? 1u : 0u;
     h.out = out;
     h.elem_bytes = (int32_t)sizeof(U128);
     h.wide = 1;
     const size_t roff = rt::blob_ranges_offset();
+    const JobHeader *job = (const JobHeader *)c->d_blob.p;
+    const RangeDesc *ranges = (const RangeDesc *)(c->d_blob.p + roff);
     hipError_t e = hipMemcpyAsync(c->d_blob.p, &h, sizeof h, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->d_blob.p + roff, &d, sizeof d, hipMemcpyHostToDevice, s);
@@ -503,12 +550,65 @@ int wide_job(sieve_ctx *c, const sieve_u128 &lo128, const sieve_u128 &hi128, boo
                            a.counts);
         e = hipGetLastError();
     }
+    if (e == hipSuccess && buckets) {
+        // Exact bucket layout: count the hits per tile, scan, then fill.
+        BucketArgs b;
+        memset(&b, 0, sizeof b);
+        b.job = job;
+        b.ranges = ranges;
+        b.prm = c->d_prm.p;
+        b.bcount = c->d_bcount.p;
+        b.bcursor = c->d_bcursor.p;
+        b.boff = c->d_boff.p;
+        b.counters = c->d_counters.p;
+        b.skip5 = (c->ngroups >= 1 && c->prm.cofactor_skip != SIEVE_SKIP_NONE) ? 1u : 0u;
+        b.nbits = 32 * pw;
+        b.span = 192ull * pw;
+        b.span_rcp = UINT64_MAX / b.span;
+        uint32_t win = 64;
+        while (win < std::min<uint64_t>(nt, kBucketWindow))
+            win <<= 1;
+        b.win = std::min(win, kBucketWindow);
+        b.wide = 1;
+        b.w5 = (uint32_t)(W % 5);
+        b.wlo = a.wlo;
+        b.whi = a.whi;
+        b.wm1_lo = a.wm1_lo;
+        b.wm1_hi = a.wm1_hi;
+        e = launch_zero(job, c->d_counters.p, c->d_counts.p, c->d_bcount.p, c->d_gbm.p, c->d_garrive.p, nullptr, s);
+        if (e == hipSuccess)
+            e = launch_bucket(b, 0, cus, s);
+        BucketScanArgs sc;
+        sc.job = job;
+        sc.bcount = c->d_bcount.p;
+        sc.boff = c->d_boff.p;
+        sc.bcursor = c->d_bcursor.p;
+        if (e == hipSuccess)
+            e = launch_bucket_scan(sc, s);
+        unsigned long long total = 0;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&total, c->d_boff.p + nt, sizeof total, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (e == hipSuccess && total > c->cap_bdata) {
+            c->cap_bdata = std::max<uint64_t>(total, c->cap_bdata + c->cap_bdata / 2);
+            c->d_bdata.release();
+            c->gen++;  // captured graphs hold the old address
+            if (!c->d_bdata.reserve(c->cap_bdata))
+                return SIEVE_E_NOMEM;
+        }
+        b.bdata = c->d_bdata.p;
+        if (e == hipSuccess)
+            e = launch_bucket(b, 1, cus, s);
+        a.bdata = c->d_bdata.p;
+        a.boff = c->d_boff.p;
+    }
     if (e == hipSuccess && a.n_mid > a.first_mark) {
         hipLaunchKernelGGL(k_wide_prep, dim3(std::min<uint32_t>(cus * 4, (a.n_mid + 255) / 256)), dim3(256), 0, s,
                            a, c->d_wr.p);
         e = hipGetLastError();
     }
-    const uint64_t n_large = (uint64_t)(a.n_act - a.n_mid) + n_ext;
+    const uint64_t n_large = (uint64_t)(a.n_act - a.k_atomic) + n_ext;
     if (e == hipSuccess && n_large) {
         const uint64_t blocks = std::min<uint64_t>((n_large + kLargeThreads - 1) / kLargeThreads, cus * 32ull);
         hipLaunchKernelGGL(k_wide_large, dim3((uint32_t)blocks), dim3(kLargeThreads), 0, s, a);
@@ -521,8 +621,6 @@ int wide_job(sieve_ctx *c, const sieve_u128 &lo128, const sieve_u128 &hi128, boo
         hipLaunchKernelGGL(k_wide_tile, dim3((uint32_t)std::min<uint64_t>(nt, cus)), dim3(kWideThreads), lds, s, a);
         e = hipGetLastError();
     }
-    const JobHeader *job = (const JobHeader *)c->d_blob.p;
-    const RangeDesc *ranges = (const RangeDesc *)(c->d_blob.p + roff);
     SegArgs g;
     g.job = job;
     g.ranges = ranges;
@@ -564,16 +662,83 @@ int wide_job(sieve_ctx *c, const sieve_u128 &lo128, const sieve_u128 &hi128, boo
                            hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
         e = hipStreamSynchronize(s);
-    if (e == hipSuccess)
-        e = hipEventRecord(c->last_ev, s);
     if (e != hipSuccess)
         return rt::hip_status(e);
-    c->last_stream = s;
-    c->last_valid = true;
     if (res[1])
         return SIEVE_E_DEVICE;
-    *count = res[0];
+    count = res[0];
     return status;
+}
+
+// One wide window: count (list false) or list into out.  A window whose
+// bucket entries would exceed the context's bucket memory runs as pieces of
+// whole tiles, each sieved from its own base; counts add up and list pieces
+// follow each other in the output.
+int wide_job(sieve_ctx *c, const sieve_u128 &lo128, const sieve_u128 &hi128, bool list, U128 *out, uint64_t cap,
+             uint64_t *count, hipStream_t stream)
+{
+    const u128 L = to_u128(lo128), H = to_u128(hi128);
+    if (L < (u128)SIEVE_WIDE_MIN_LO || H < L || H - L > (u128)SIEVE_WIDE_MAX_SPAN)
+        return SIEVE_E_INVAL;
+    *count = 0;
+    if (H == L)
+        return SIEVE_OK;
+    uint64_t root, n_ext;
+    uint32_t n_act;
+    int st = window_primes(c, H, root, n_act, n_ext);
+    if (st != SIEVE_OK)
+        return st;
+    hipStream_t s = stream ? stream : c->stream;
+    // The scratch is shared with the context's stream-ordered jobs.
+    if (c->last_valid && hipEventSynchronize(c->last_ev) != hipSuccess) {
+        (void)hipGetLastError();
+        return SIEVE_E_DEVICE;
+    }
+    // Tiles per piece from the expected bucket entries per tile: each
+    // resident prime p past the LDS-marked ones hits a plane of nbits bits
+    // nbits / p times, plus a margin of 8 standard deviations.
+    const uint32_t pw = c->prm.segment_bytes / 8;
+    const u128 span = (u128)192 * pw;
+    const u128 W = L - L % 6;
+    const uint64_t nt_all = (uint64_t)((H - W + span - 1) / span);
+    const uint32_t n_mid = std::min(mid_primes(c, root, nt_all), std::max(n_act, c->first_mark));
+    const uint32_t n_big = std::max(n_mid, bucket_end(c, root, nt_all * pw));
+    uint64_t tiles = nt_all;
+    if (n_big > n_mid) {
+        // pieces of equal size: each costs a pass over every bucketed prime
+        const double E = 2.0 * 32.0 * pw * (c->inv_prefix[n_big] - c->inv_prefix[n_mid]);
+        const double per_tile = E + 8.0 * std::sqrt(E) + 64.0;
+        const uint64_t fit = std::max<uint64_t>(1, (uint64_t)((double)c->bucket_budget / per_tile));
+        const uint64_t pieces = (nt_all + fit - 1) / fit;
+        tiles = (nt_all + pieces - 1) / pieces;
+    }
+    uint64_t total = 0;
+    bool over = false;
+    u128 a = L;
+    for (uint64_t k = 0; a < H; ++k) {
+        u128 b = W + (u128)(k + 1) * tiles * span;
+        if (b > H)
+            b = H;
+        const bool lst = list && !over;
+        uint64_t n = 0;
+        st = wide_piece(c, a, b, lst, lst ? out + total : nullptr, lst ? cap - total : 0, n, s);
+        if (st == SIEVE_E_CAPACITY) {
+            over = true;  // keep counting the rest for the required size
+            st = SIEVE_OK;
+        }
+        if (st != SIEVE_OK)
+            return st;
+        total += n;
+        a = b;
+    }
+    if (hipEventRecord(c->last_ev, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return SIEVE_E_DEVICE;
+    }
+    c->last_stream = s;
+    c->last_valid = true;
+    *count = total;
+    return over ? SIEVE_E_CAPACITY : SIEVE_OK;
 }
 
 }  // namespace
