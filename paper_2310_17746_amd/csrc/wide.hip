@@ -11,15 +11,15 @@
 //     first multiples at or past W, or P*P when that lies past W (Sec. 2.4);
 //   * the presieve phases (W / 6) mod period of the pattern groups;
 //   * the output, W + offset as 128-bit values.
-// lo >= 2^40 keeps every prime marked in LDS (at most 16 plane lengths,
-// below 2^24) below W, so the first multiple at or past W is never the prime
+// lo >= 2^40 keeps every prime marked in LDS (at most 4 plane lengths,
+// below 2^22) below W, so the first multiple at or past W is never the prime
 // itself; those primes start there with no square test (from W instead of
 // P * P they only mark composites twice).  It also keeps 1, 2, 3 and the
 // presieved primes out of every window.
 //
 // Work split by prime size:
 //   * 5..73: the presieve pattern tables, which initialise each tile's planes;
-//   * up to 16 plane lengths: LDS marks tile by tile, each start from the
+//   * up to 4 plane lengths: LDS marks tile by tile, each start from the
 //     window residue plus the tile's offset (one 64-by-32-bit reduction);
 //     the smallest of them split over several lanes as in the 64-bit path;
 //   * the next resident primes, with at least two hits in the window (P
@@ -62,7 +62,7 @@ constexpr uint32_t kWideThreads = 1024;      // tile kernel
 constexpr uint32_t kLargeThreads = 256;      // large-prime kernel
 constexpr uint32_t kMaxTileChunks = 64;      // bitmap chunks per tile (pw <= 32768)
 constexpr uint64_t kExtSample = 4096;        // extension primes per host sample
-constexpr uint64_t kMidPlanes = 16;          // LDS-marked primes: up to this many plane lengths
+constexpr uint64_t kMidPlanes = 4;           // LDS-marked primes: up to this many plane lengths
 
 struct WideArgs {
     uint64_t wlo, whi;          // W, the window base (a multiple of 6)
@@ -414,11 +414,12 @@ int window_primes(sieve_ctx *c, u128 H, uint64_t &root, uint32_t &n_act, uint64_
     return need_ext ? ext_upto(c, root, n_ext) : SIEVE_OK;
 }
 
-// Resident primes marked in LDS tile by tile: up to kMidPlanes plane lengths.
-// Measured, a start costs about a sixteenth of an atomic OR to HBM, so the
-// break-even of per-tile starts lies near 16 plane lengths (one hit per prime
-// per 16 tiles).  A window of few tiles keeps most CUs out of the tile
-// kernel, so there the cut-off shrinks with the tiles per CU.
+// Resident primes marked in LDS tile by tile: up to kMidPlanes plane lengths
+// (the larger ones go through the buckets).  Measured on the count of
+// [2^64, 2^64 + 10^10) and of 10^9: 1, 2, 4, 8 and 16 plane lengths give
+// 25.3 / 3.79, 24.7 / 3.71, 24.4 / 3.71, 24.9 / 3.84 and 24.7 / 4.16 ms.  A
+// window of few tiles keeps most CUs out of the tile kernel, so there the
+// cut-off shrinks with the tiles per CU.
 uint32_t mid_primes(const sieve_ctx *c, uint64_t root, uint64_t nt)
 {
     const uint32_t pw = c->prm.segment_bytes / 8;
