@@ -192,3 +192,20 @@ def test_wide_list_at_bench_size(sv):
             k = int(np.searchsorted(low, np.uint64(v)))
             assert (k < n and int(low[k]) == v) == brute.is_prime_mr(T64 + v), v
 
+
+
+def test_every_wheel_candidate_by_miller_rabin(sv):
+    """Deterministic Miller-Rabin (first twelve prime bases, exact below
+    3.18e23) on every wheel candidate of a window just above 2^64, straight
+    against the GPU list: a candidate is listed exactly when it is prime."""
+    lo, hi = T64 + 10 ** 12 + 1, T64 + 10 ** 12 + 300001
+    got = set(pkg.wide_values(sv.list_wide(lo, hi)))
+    v = lo + (1 - lo % 6) % 6  # first candidate = 1 (mod 6)
+    n = 0
+    while v < hi:
+        for c in (v, v + 4):
+            if lo <= c < hi:
+                assert (c in got) == brute.is_prime_mr(c), c
+                n += 1
+        v += 6
+    assert n >= 99000 and all(lo <= p < hi and p % 6 in (1, 5) for p in got)
