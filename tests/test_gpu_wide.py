@@ -199,6 +199,8 @@ def test_every_wheel_candidate_by_miller_rabin(sv):
     3.18e23) on every wheel candidate of a window just above 2^64, straight
     against the GPU list: a candidate is listed exactly when it is prime."""
     lo, hi = T64 + 10 ** 12 + 1, T64 + 10 ** 12 + 300001
+    sv.ensure_base_wide_for(hi)  # isqrt(hi - 1) = 2^32 + 116: the extension list starts here
+    assert sv.ext_limit >= 2 ** 32 + 116
     got = set(pkg.wide_values(sv.list_wide(lo, hi)))
     v = lo + (1 - lo % 6) % 6  # first candidate = 1 (mod 6)
     n = 0
