@@ -13,7 +13,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "../../include/sieve_probe.h"
+#include "sieve_probe.h"
 
 namespace {
 

@@ -31,7 +31,7 @@
 #include <unordered_map>
 #include <vector>
 
-#include "../../include/sieve.h"
+#include "sieve.h"
 #include "runtime.h"
 
 namespace {
