@@ -116,7 +116,7 @@ typedef struct sieve_ctx sieve_ctx;
  *                    that each lane's hits share one bit position and need
  *                    one add each; SIEVE_DENSE_NEVER disables it.
  *   bucket_mem_mb    device memory one job may use for bucket entries, in
- *                    MiB (default 4096).  A job whose estimate is larger runs
+ *                    MiB (default 16384).  A job whose estimate is larger runs
  *                    as a sequence of jobs over tile-aligned pieces of its
  *                    ranges; results are the same.
  *   visit_order      order in which the sieve kernel's workgroups take the

@@ -148,7 +148,7 @@ void fill_defaults(sieve_params &p)
     if (!p.wg_per_cu)
         p.wg_per_cu = std::max<uint32_t>(1, std::min<uint32_t>(4, (160 * 1024) / p.segment_bytes));
     if (!p.bucket_mem_mb)
-        p.bucket_mem_mb = 4096;
+        p.bucket_mem_mb = 16384;  // 16 GiB of the 288 GiB HBM
     if (!p.dense_hits)
         p.dense_hits = 512;
 }
