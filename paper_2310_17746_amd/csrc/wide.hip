@@ -366,14 +366,18 @@ using u128 = unsigned __int128;
 
 u128 to_u128(const sieve_u128 &x) { return ((u128)x.hi << 64) | x.lo; }
 
+// floor(sqrt(n)) for any 128-bit n: a long double estimate (clamped below
+// 2^64, since the root of n near 2^128 rounds up to 2^64), corrected by
+// exact products; (s + 1)^2 is formed only while s + 1 < 2^64.
 uint64_t isqrt_u128(u128 n)
 {
     if (n < 2)
         return (uint64_t)n;
-    uint64_t s = (uint64_t)sqrtl((long double)n);
+    const long double r = sqrtl((long double)n);
+    uint64_t s = r >= 18446744073709551615.0L ? UINT64_MAX : (uint64_t)r;
     while ((u128)s * s > n)
         --s;
-    while ((u128)(s + 1) * (s + 1) <= n)
+    while (s < UINT64_MAX && (u128)(s + 1) * (s + 1) <= n)
         ++s;
     return s;
 }

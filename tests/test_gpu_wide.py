@@ -211,3 +211,32 @@ def test_every_wheel_candidate_by_miller_rabin(sv):
                 n += 1
         v += 6
     assert n >= 99000 and all(lo <= p < hi and p % 6 in (1, 5) for p in got)
+
+
+def test_pieces_under_a_small_bucket_budget(sv):
+    """With 1 MiB of bucket memory a window runs as many equal pieces, each
+    sieved from its own base: the same list and count as one piece, the
+    oracle's list, and a short output still reports the full count."""
+    lo, hi = T64 + 7, T64 + 2 * 10 ** 7 + 3
+    want = oracle.primes_wide(lo, hi)
+    one = sv.list_wide(lo, hi).cpu().numpy().view(np.uint64).reshape(-1, 2)
+    with pkg.Sieve(0, dict(bucket_mem_mb=1)) as s:
+        s.base_primes((1 << 32) - 1)
+        print("wide: pieces [%d, %d)" % (lo, hi), flush=True)
+        got = s.list_wide(lo, hi).cpu().numpy().view(np.uint64).reshape(-1, 2)
+        assert np.array_equal(got, want) and np.array_equal(one, want)
+        assert s.count_wide(lo, hi) == len(want)
+        out = torch.empty((len(want) // 2, 2), dtype=torch.int64, device="cuda")
+        with pytest.raises(pkg.SieveError) as e:
+            s.list_wide(lo, hi, out=out)
+        assert e.value.code == pkg.SIEVE_E_CAPACITY
+
+
+def test_values_near_2_127(sv):
+    # the 128-bit square root of such bounds needs base primes near 2^63.5
+    for lo in (1 << 127, (1 << 128) - 100):
+        with pytest.raises(pkg.SieveError) as e:
+            sv.count_wide(lo, lo + 10)
+        assert e.value.code == pkg.SIEVE_E_RANGE
+    with pytest.raises(ValueError):
+        pkg.U128.of(1 << 128)
