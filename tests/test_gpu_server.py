@@ -2,6 +2,7 @@
 result alone (bit-exact) and the oracle's; admission by output memory,
 cancellation and scheduled arrivals behave as documented."""
 import time
+from math import isqrt
 
 import numpy as np
 import pytest
@@ -122,3 +123,22 @@ def test_scheduled_arrivals(sv):
             c = got[k]
             assert c["count"] == want
             assert c["t_arrival_ns"] == arr[k] and c["t_admit_ns"] >= arr[k] and c["t_done_ns"] >= c["t_admit_ns"]
+
+
+@pytest.mark.parametrize("overlap", [0, 1])
+def test_base_primes_grow_while_steps_run(overlap):
+    """A fresh context with small base primes: requests arrive that need more
+    of them while earlier steps are on the device (with overlap, one is still
+    in flight when the store is re-installed).  Every count is the oracle's."""
+    reqs = [(10 ** 6, 10 ** 6 + 10 ** 6), (10 ** 10, 10 ** 10 + 10 ** 6), (10 ** 12, 10 ** 12 + 10 ** 6),
+            (10 ** 14, 10 ** 14 + 10 ** 6), (2, 10 ** 9 + 1), (10 ** 15, 10 ** 15 + 10 ** 5)]
+    with pkg.Sieve(0) as s:
+        s.base_primes(1 << 16)
+        with pkg.Server(s, step_tiles=64, quantum_tiles=4, overlap=overlap) as srv:
+            for i, (lo, hi) in enumerate(reqs):
+                srv.submit(lo, hi, 0, i)
+            got = _drain(srv, len(reqs))
+        for i, (lo, hi) in enumerate(reqs):
+            assert got[i]["status"] == 0 and got[i]["count"] == oracle.count(lo, hi), (i, lo, hi)
+        assert s.base_limit >= max(isqrt(hi - 1) for _, hi in reqs)
+

@@ -240,3 +240,31 @@ def test_values_near_2_127(sv):
         assert e.value.code == pkg.SIEVE_E_RANGE
     with pytest.raises(ValueError):
         pkg.U128.of(1 << 128)
+
+
+@pytest.fixture(scope="module")
+def param_window():
+    lo, hi = T64 + 5, T64 + 3 * 10 ** 6 + 11
+    return lo, hi, oracle.primes_wide(lo, hi)
+
+
+@pytest.mark.parametrize("params", [
+    dict(segment_bytes=8192, block_threads=256),
+    dict(segment_bytes=53248, block_threads=512, wg_per_cu=3),
+    dict(presieve_groups=pkg.PRESIEVE_NONE, cofactor_skip=pkg.SKIP_NONE),
+    dict(presieve_groups=1, cofactor_skip=pkg.SKIP_ALL, split_hits=8),
+    dict(dense_hits=pkg.DENSE_NEVER, split_hits=256),
+    dict(segment_bytes=131072, block_threads=1024, bucket_mem_mb=1),
+])
+def test_wide_under_other_parameters(param_window, params):
+    """Tile size, presieve groups, cofactor skip, split and dense items and the
+    bucket budget all shape the wide path's work: the list stays the oracle's."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    lo, hi, want = param_window
+    print("wide params: %s" % params, flush=True)
+    with pkg.Sieve(0, params) as s:
+        s.base_primes((1 << 32) - 1)
+        got = s.list_wide(lo, hi).cpu().numpy().view(np.uint64).reshape(-1, 2)
+        assert np.array_equal(got, want), params
+        assert s.count_wide(lo, hi) == len(want)
