@@ -492,6 +492,18 @@ int sieve_submit(sieve_server *srv, uint64_t lo, uint64_t hi, int mode, uint64_t
 int sieve_submit_at(sieve_server *srv, uint64_t lo, uint64_t hi, int mode, uint64_t tag,
                     uint64_t t_arrival_ns);
 
+/* As sieve_submit, with the list written straight into caller-owned device
+ * memory instead of the server's arena (a submit that takes out and cap):
+ * for mode 1, out_dev (required, aligned to elem_bytes) receives the
+ * primes of [lo, hi) in increasing order, at most cap elements.  No arena
+ * space is reserved and nothing is to be fetched; the completion's count is
+ * the number of primes.  If that exceeds cap the request still counts every
+ * piece, completes with SIEVE_E_CAPACITY and the full count, and nothing is
+ * guaranteed written.  The caller keeps out_dev alive until the completion.
+ * For mode 0 out_dev and cap are ignored. */
+int sieve_submit_out(sieve_server *srv, uint64_t lo, uint64_t hi, int mode, void *out_dev, uint64_t cap,
+                     uint64_t tag);
+
 /* Moves up to max finished requests into buf; waits up to wait_ms for at
  * least one (0: no wait).  *n_out receives the number moved. */
 int sieve_poll(sieve_server *srv, sieve_completion *buf, int max, int wait_ms, int *n_out);

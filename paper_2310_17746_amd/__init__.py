@@ -164,6 +164,7 @@ def load_library():
         "sieve_server_create": (ctypes.c_int, [_p, ctypes.POINTER(ServerParams), ctypes.POINTER(_p)]),
         "sieve_submit": (ctypes.c_int, [_p, _u64, _u64, ctypes.c_int, _u64]),
         "sieve_submit_at": (ctypes.c_int, [_p, _u64, _u64, ctypes.c_int, _u64, _u64]),
+        "sieve_submit_out": (ctypes.c_int, [_p, _u64, _u64, ctypes.c_int, _p, _u64, _u64]),
         "sieve_poll": (ctypes.c_int, [_p, ctypes.POINTER(Completion), ctypes.c_int, ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_int)]),
         "sieve_cancel": (ctypes.c_int, [_p, _u64]),
@@ -651,8 +652,17 @@ class Server:
     def now_ns(self) -> int:
         return int(self._lib.sieve_server_now_ns(self._h))
 
-    def submit(self, lo: int, hi: int, mode: int, tag: int, at_ns: int | None = None) -> None:
-        if at_ns is None:
+    def submit(self, lo: int, hi: int, mode: int, tag: int, at_ns: int | None = None, out=None) -> None:
+        """Queues [lo, hi) (mode 0 count, 1 list).  With `out` (a contiguous
+        device tensor of the server's element size) a list goes straight
+        into it, at most out.numel() elements, instead of the arena."""
+        if out is not None:
+            if at_ns is not None:
+                raise ValueError("a scheduled arrival takes the arena output")
+            if not out.is_contiguous():
+                raise ValueError("out must be contiguous")
+            code = self._lib.sieve_submit_out(self._h, lo, hi, mode, out.data_ptr(), out.numel(), tag)
+        elif at_ns is None:
             code = self._lib.sieve_submit(self._h, lo, hi, mode, tag)
         else:
             code = self._lib.sieve_submit_at(self._h, lo, hi, mode, tag, at_ns)

@@ -860,8 +860,6 @@ int run_job_once(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *h
 {
     int st;
     const uint64_t nlist = pl.nlist;
-    if (nlist && !out)
-        return SIEVE_E_INVAL;
     st = ensure_capacity(c, n, pl.nchunks, pl.ntiles, pl.gtiles);
     if (st != SIEVE_OK)
         return st;
@@ -1124,8 +1122,6 @@ int run_job(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, co
     if (pl.best <= budget)
         return run_job_once(c, n, lo, hi, mode, off, cap, elem_bytes, out, counts, status, stream, use_graph, pl,
                             async_ok);
-    if (pl.nlist && !out)
-        return SIEVE_E_INVAL;
     const uint64_t span = (uint64_t)kValsPerWord * (c->prm.segment_bytes / 8);
     std::vector<RangeDesc> d0 = pl.ranges;  // the whole ranges' plans
     std::vector<uint64_t> cur(lo, lo + n), acc(n, 0), tot(n, 0), per(n);

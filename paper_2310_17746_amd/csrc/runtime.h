@@ -186,7 +186,10 @@ uint64_t isqrt_host(uint64_t n);
 // Tile plan of [lo, hi) for pw plane words per tile.
 void plan_range(uint64_t lo, uint64_t hi, uint32_t pw, uint64_t &ntiles, uint64_t &base, uint32_t &last_words);
 // One job over n ranges (see api.hip) on `stream` (NULL: the context stream).
-// counts/status are host arrays of n entries (may be NULL).  Synchronous
+// counts/status are host arrays of n entries (may be NULL).  List range i
+// writes its primes from element off[i] of `out`; `out` may be NULL, and
+// off[i] then is the output's device address divided by elem_bytes (so that
+// ranges of one job can write to unrelated buffers).  Synchronous
 // unless async_ok: then a job that needs no host decision mid-way returns
 // once enqueued, and counts/status are written when the stream reaches its
 // end.

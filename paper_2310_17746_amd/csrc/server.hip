@@ -107,6 +107,8 @@ struct Request {
     uint32_t inflight = 0;    // pieces in enqueued steps
     uint32_t issued = 0;      // pieces handed out so far
     int err = SIEVE_OK;       // first failed piece's status
+    void *uout = nullptr;     // caller's output (sieve_submit_out), else the arena
+    bool over = false;        // caller's output too small: counting the rest only
     uint64_t count = 0;
     uint64_t off_bytes = 0, cap_elems = 0, arena_bytes = 0;
     bool has_arena = false;
@@ -191,10 +193,14 @@ bool request_done(const Request *r)
     return r->ntiles == 0 ? r->issued > 0 : r->tiles_done >= r->ntiles;
 }
 
+// Whether r lists its next piece (a caller's buffer found too small turns
+// the rest of the request into counting).
+bool listing(const Request *r) { return r->mode && !r->over; }
+
 // Whether r may take a piece in the step being planned.
 bool plannable(const Request *r)
 {
-    if (r->cancelled || r->err != SIEVE_OK || (r->mode && r->inflight))
+    if (r->cancelled || r->err != SIEVE_OK || (listing(r) && r->inflight))
         return false;
     return r->ntiles == 0 ? r->issued == 0 : r->next_tile < r->ntiles;
 }
@@ -217,9 +223,12 @@ void apply_step(sieve_server *s, Step &st)
         const int stt = st.rc != SIEVE_OK ? st.rc : st.status[i];
         s->st.tiles += st.pieces[i].second;
         s->st.ints += st.hi[i] - st.lo[i];
-        if (stt == SIEVE_OK) {
+        if (stt == SIEVE_OK || (stt == SIEVE_E_CAPACITY && r->uout)) {
+            // (a piece that overflowed the caller's buffer still counted all
+            // of its primes; the request goes on counting)
             r->count += st.counts[i];
             r->tiles_done += st.pieces[i].second;
+            r->over = r->over || stt == SIEVE_E_CAPACITY;
         } else if (r->err == SIEVE_OK) {
             r->err = stt;
         }
@@ -229,7 +238,7 @@ void apply_step(sieve_server *s, Step &st)
         if (r->err != SIEVE_OK)
             fin = r->err;
         else if (request_done(r))
-            fin = SIEVE_OK;
+            fin = r->over ? SIEVE_E_CAPACITY : SIEVE_OK;
         else if (r->cancelled)
             fin = SIEVE_E_CANCELLED;
         if (fin != 1) {
@@ -294,7 +303,7 @@ void scheduler(sieve_server *s)
                         complete_locked(s, r, SIEVE_E_CANCELLED, t);
                         continue;
                     }
-                    if (r->mode) {
+                    if (r->mode && !r->uout) {
                         r->cap_elems = sieve_list_bound(r->lo, r->hi);
                         r->arena_bytes = std::max<uint64_t>(r->cap_elems * eb, 1);
                         if (r->arena_bytes > s->p.out_budget_bytes) {
@@ -356,9 +365,14 @@ void scheduler(sieve_server *s)
                     const uint64_t k0 = r->next_tile, k1 = k0 + take;
                     st.lo.push_back(k0 == 0 ? r->lo : r->base + k0 * S);
                     st.hi.push_back(r->ntiles == 0 || k1 == r->ntiles ? r->hi : r->base + k1 * S);
-                    st.mode.push_back((uint8_t)r->mode);
-                    st.off.push_back(r->mode ? r->off_bytes / eb + r->count : 0);
-                    st.cap.push_back(r->mode ? r->cap_elems - r->count : 0);
+                    // list pieces write at absolute element addresses (the job's
+                    // output base is NULL): the arena or the caller's buffer
+                    const bool lst = listing(r);
+                    const uint64_t dst = (uint64_t)(uintptr_t)(r->uout ? (unsigned char *)r->uout
+                                                                       : s->arena_base + r->off_bytes);
+                    st.mode.push_back((uint8_t)lst);
+                    st.off.push_back(lst ? dst / eb + r->count : 0);
+                    st.cap.push_back(lst ? r->cap_elems - r->count : 0);
                     st.pieces.emplace_back(r, take);
                     r->next_tile = k1;
                     r->inflight++;
@@ -391,7 +405,7 @@ void scheduler(sieve_server *s)
             st.timed = st.ev0 && st.ev1 && hipEventRecord(st.ev0, c->stream) == hipSuccess;
             if (st.rc == SIEVE_OK)
                 st.rc = sieve::rt::run_job(c, m, st.lo.data(), st.hi.data(), st.mode.data(), st.off.data(),
-                                           st.cap.data(), (int)eb, s->arena_base, st.counts.data(),
+                                           st.cap.data(), (int)eb, nullptr, st.counts.data(),
                                            st.status.data(), c->stream, c->prm.use_graph != 0,
                                            s->p.overlap != 0);
             st.buckets = c->bucket_jobs != bj;
@@ -414,9 +428,12 @@ void scheduler(sieve_server *s)
     }
 }
 
-int submit(sieve_server *s, uint64_t lo, uint64_t hi, int mode, uint64_t tag, bool at, uint64_t t_arr)
+int submit(sieve_server *s, uint64_t lo, uint64_t hi, int mode, uint64_t tag, bool at, uint64_t t_arr,
+           void *uout = nullptr, uint64_t ucap = 0)
 {
     if (!s || lo > hi || hi > SIEVE_MAX_HI || (mode != 0 && mode != 1))
+        return SIEVE_E_INVAL;
+    if (mode && uout && (uintptr_t)uout % s->p.elem_bytes)
         return SIEVE_E_INVAL;
     if (mode && s->p.elem_bytes == 4 && hi > lo && hi - 1 > 0xFFFFFFFFull)
         return SIEVE_E_DTYPE;
@@ -429,6 +446,10 @@ int submit(sieve_server *s, uint64_t lo, uint64_t hi, int mode, uint64_t tag, bo
     r->lo = lo;
     r->hi = hi;
     r->mode = mode;
+    if (mode && uout) {
+        r->uout = uout;
+        r->cap_elems = ucap;
+    }
     sieve::rt::plan_range(lo, hi, s->ctx->prm.segment_bytes / 8, r->ntiles, r->base, r->last_words);
     {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -507,6 +528,14 @@ int sieve_submit(sieve_server *srv, uint64_t lo, uint64_t hi, int mode, uint64_t
 int sieve_submit_at(sieve_server *srv, uint64_t lo, uint64_t hi, int mode, uint64_t tag, uint64_t t_arrival_ns)
 {
     return submit(srv, lo, hi, mode, tag, true, t_arrival_ns);
+}
+
+int sieve_submit_out(sieve_server *srv, uint64_t lo, uint64_t hi, int mode, void *out_dev, uint64_t cap,
+                     uint64_t tag)
+{
+    if (mode && !out_dev)
+        return SIEVE_E_INVAL;
+    return submit(srv, lo, hi, mode, tag, false, 0, out_dev, cap);
 }
 
 int sieve_poll(sieve_server *srv, sieve_completion *buf, int max, int wait_ms, int *n_out)

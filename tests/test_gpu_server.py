@@ -142,3 +142,31 @@ def test_base_primes_grow_while_steps_run(overlap):
             assert got[i]["status"] == 0 and got[i]["count"] == oracle.count(lo, hi), (i, lo, hi)
         assert s.base_limit >= max(isqrt(hi - 1) for _, hi in reqs)
 
+
+
+@pytest.mark.parametrize("overlap", [0, 1])
+def test_submit_into_caller_buffers(sv, overlap):
+    """sieve_submit_out: lists written straight into caller-owned tensors,
+    beside arena lists and a long count; a buffer one element short reports
+    SIEVE_E_CAPACITY with the full count."""
+    reqs = [(10 ** 9, 10 ** 9 + 2 * 10 ** 6), (10 ** 11 - 5 * 10 ** 6, 10 ** 11 + 10 ** 6),
+            (3, 5 * 10 ** 5), (10 ** 10, 10 ** 10 + 4 * 10 ** 7)]
+    want = [oracle.primes(lo, hi, elem_bytes=8) for lo, hi in reqs]
+    outs = [torch.full((len(w) + 3,), -1, dtype=torch.int64, device="cuda") for w in want]
+    short = torch.empty(len(want[3]) - 1, dtype=torch.int64, device="cuda")
+    with pkg.Server(sv, step_tiles=64, quantum_tiles=4, overlap=overlap) as srv:
+        srv.submit(2, 10 ** 10 + 1, 0, 100)
+        for i, (lo, hi) in enumerate(reqs[:3]):
+            srv.submit(lo, hi, 1, i, out=outs[i])
+        srv.submit(reqs[3][0], reqs[3][1], 1, 3, out=short)
+        srv.submit(reqs[0][0], reqs[0][1], 1, 50)  # the same range through the arena
+        got = _drain(srv, 6)
+        for i in range(3):
+            assert got[i]["status"] == 0 and got[i]["count"] == len(want[i]), i
+            host = outs[i].cpu().numpy().view(np.uint64)
+            assert np.array_equal(host[:len(want[i])], want[i]), i
+            assert np.all(outs[i][len(want[i]):].cpu().numpy() == -1)  # nothing past the list
+        assert got[3]["status"] == pkg.SIEVE_E_CAPACITY and got[3]["count"] == len(want[3])
+        assert got[50]["status"] == 0
+        assert np.array_equal(_u(srv.fetch(50, got[50]["count"])), want[0])
+        assert got[100]["status"] == 0 and got[100]["count"] == 455052511
