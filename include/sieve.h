@@ -169,7 +169,10 @@ int sieve_default_params(sieve_params *p);
  * Creates a context on HIP device `device` (must be gfx950).  The context
  * owns the resident base primes (the paper's Sieve Data Store, Sec. 4),
  * presieve pattern tables, scratch, captured graphs and a stream.
- * p == NULL selects the defaults.  On success *ctx is set.
+ * p == NULL selects the defaults: one 1024-thread workgroup per CU with a
+ * 152 KiB tile, the best single shape measured over the workloads (the
+ * binding's autotuner, autotune.py, picks a shape per workload class on the
+ * GPU at hand and passes it here).  On success *ctx is set.
  */
 int sieve_create(sieve_ctx **ctx, int device, const sieve_params *p);
 
