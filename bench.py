@@ -263,7 +263,19 @@ def bench_batch(pkg, torch, params, workloads, steps=3):
     s.list_batch(lo, hi, mode, out, off, cap, elem_bytes=8)
     torch.cuda.synchronize()
     sieve_ms, post_ms, bucket_ms, jobs = s.timing_all()
+    # the same ranges one call each, device time only (the same events,
+    # summed over the 4096 jobs): the batching gain without host overhead
+    s.set_timing(True)
+    for a, b, m, o, c in zip(lo.tolist(), hi.tolist(), mode.tolist(), off.tolist(), cap.tolist()):
+        if m:
+            s.list(a, b, out=out[o:o + max(c, 1)], elem_bytes=8)
+        else:
+            s.count(a, b)
+    torch.cuda.synchronize()
+    r_sieve, r_post, r_bucket, r_jobs = s.timing_all()
     s.close()
+    dev_batch = sieve_ms + post_ms + bucket_ms
+    dev_single = r_sieve + r_post + r_bucket
     ints = int((hi - lo).sum())
     primes = int(counts.sum())
     return {"workload": "4096 ranges (seed 0): lo log-uniform [1e6, 1e15], length log-uniform "
@@ -273,6 +285,8 @@ def bench_batch(pkg, torch, params, workloads, steps=3):
             "primes_per_s": round(primes / dt, 1),
             "per_range_ms": round(dt_single * 1e3, 3),
             "batched_vs_per_range": round(dt_single / dt, 3),
+            "device_ms": {"batched": round(dev_batch, 3), "per_range_sum": round(dev_single, 3),
+                          "per_range_jobs": r_jobs, "batched_vs_per_range": round(dev_single / dev_batch, 3)},
             "phases_ms": {"sieve": round(sieve_ms, 3), "bucket_fill": round(bucket_ms, 3),
                           "scan_and_compaction": round(post_ms, 3), "jobs": jobs}}
 
