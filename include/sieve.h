@@ -455,6 +455,11 @@ typedef struct sieve_server_params {
     uint32_t overlap;          /* 1: step k + 1 is planned and enqueued while step k runs
                                   (hides host planning, costs arrivals one step of waiting);
                                   0 (default): one step on the device at a time */
+    uint32_t restart_walks;    /* 1: every piece of a request starts its bucket walks afresh;
+                                  0 (default): a request cut into pieces keeps its large
+                                  primes' bucket walk state on the device from one piece to
+                                  the next (Sec. 2.4's incremental state): 16 bytes per bucket
+                                  prime, twice, while the request is active */
 } sieve_server_params;
 
 /* One finished request.  Times are nanoseconds on the server's steady clock
@@ -480,6 +485,9 @@ typedef struct sieve_server_stats {
     uint64_t queued, active;  /* at the time of the call */
     uint64_t bucket_steps;    /* steps whose job used the bucket sieve */
     uint64_t overlap_steps;   /* steps enqueued while the previous step was still running */
+    uint64_t resumed_walks;   /* pieces whose bucket walks resumed from the state their
+                                 request's previous piece left on the device */
+    uint64_t walk_bytes;      /* device memory held for resident walk state (pooled) */
 } sieve_server_stats;
 
 /* Creates a server on ctx (p == NULL: defaults).  *srv is set on success. */

@@ -87,7 +87,7 @@ class ServerParams(ctypes.Structure):
     _fields_ = [("out_budget_bytes", ctypes.c_uint64), ("max_active", ctypes.c_uint32),
                 ("step_tiles", ctypes.c_uint32), ("quantum_tiles", ctypes.c_uint32),
                 ("elem_bytes", ctypes.c_uint32), ("max_queue", ctypes.c_uint32),
-                ("overlap", ctypes.c_uint32)]
+                ("overlap", ctypes.c_uint32), ("restart_walks", ctypes.c_uint32)]
 
 
 class Completion(ctypes.Structure):
@@ -103,7 +103,8 @@ class Completion(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in ("steps", "tiles", "ints", "completed", "busy_ns",
                                                "elapsed_ns", "arena_peak_bytes", "queued", "active",
-                                               "bucket_steps", "overlap_steps")]
+                                               "bucket_steps", "overlap_steps", "resumed_walks",
+                                               "walk_bytes")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

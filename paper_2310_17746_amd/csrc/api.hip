@@ -36,6 +36,7 @@ hipError_t launch_compact(const CompactArgs &a, uint32_t grid, hipStream_t s);
 
 using namespace sieve;
 using sieve::rt::DevBuf;
+using sieve::rt::WalkSpec;
 
 namespace {
 
@@ -492,15 +493,17 @@ int make_plan(const sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct BlobLayout {
-    size_t ranges, visit, total;
+    size_t ranges, visit, links, total;
 };
 
 BlobLayout blob_layout(uint64_t nranges)
 {
     BlobLayout L;
+    const uint64_t n = std::max<uint64_t>(nranges, 1);
     L.ranges = align_up(sizeof(JobHeader), 256);
-    L.visit = align_up(L.ranges + sizeof(RangeDesc) * std::max<uint64_t>(nranges, 1), 256);
-    L.total = align_up(L.visit + sizeof(VisitEntry) * std::max<uint64_t>(nranges, 1), 256);
+    L.visit = align_up(L.ranges + sizeof(RangeDesc) * n, 256);
+    L.links = align_up(L.visit + sizeof(VisitEntry) * n, 256);
+    L.total = align_up(L.links + sizeof(WalkLink) * n, 256);
     return L;
 }
 
@@ -676,6 +679,7 @@ hipError_t enqueue_phase(sieve_ctx *c, hipStream_t s, int phase, bool timed, boo
     b.span_rcp = UINT64_MAX / b.span;
     b.win = c->bucket_win ? c->bucket_win : kBucketWindow;
     b.tally = c->d_tally.p;  // allocated in the debug build only
+    b.links = (const WalkLink *)(c->d_blob.p + L.links);
     const uint32_t bcus = (uint32_t)c->cus;
     if (phase != kPhaseRest) {
         if (timed && phase == kPhaseBucketCount && (e = hipEventRecord(c->ev[3], s)) != hipSuccess)
@@ -854,9 +858,11 @@ void deliver_results(void *arg)
 // counts/status (host, n entries) receive per-range results.  With async_ok
 // a job that needs no host decision mid-way (no bucket sieve, no timing)
 // returns once enqueued; its results are written when the stream gets there.
+// links (host, n entries, or NULL): the ranges' bucket walk links.
 int run_job_once(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, const uint8_t *mode,
                  const uint64_t *off, const uint64_t *cap, int elem_bytes, void *out, uint64_t *counts,
-                 int32_t *status, hipStream_t stream, bool use_graph, Plan &pl, bool async_ok)
+                 int32_t *status, hipStream_t stream, bool use_graph, Plan &pl, bool async_ok,
+                 const WalkLink *links = nullptr)
 {
     int st;
     const uint64_t nlist = pl.nlist;
@@ -899,6 +905,9 @@ int run_job_once(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *h
     h->nlist = (uint32_t)nlist;
     h->out = out;
     h->elem_bytes = elem_bytes;
+    h->links = links && n ? 1u : 0u;
+    if (h->links)
+        memcpy(c->h_blob + L.links, links, n * sizeof(WalkLink));
     if (n) {
         memcpy(c->h_blob + L.ranges, pl.ranges.data(), n * sizeof(RangeDesc));
         // Visit order: most Table 1 starts per work unit first (a tile of
@@ -935,6 +944,9 @@ int run_job_once(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *h
                                   hipMemcpyHostToDevice, s);
     if (e == hipSuccess && n)
         e = hipMemcpyAsync(c->d_blob.p + L.visit, c->h_blob + L.visit, n * sizeof(VisitEntry),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && h->links)
+        e = hipMemcpyAsync(c->d_blob.p + L.links, c->h_blob + L.links, n * sizeof(WalkLink),
                            hipMemcpyHostToDevice, s);
     if (e != hipSuccess)
         return hip_status(e);
@@ -1110,18 +1122,45 @@ int run_job_once(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *h
 // (offset and capacity advance by the primes already written), and once a
 // piece does not fit, the rest of that range is only counted and the range
 // reports SIEVE_E_CAPACITY with its full count.
+//
+// ws (host, n entries, or NULL) links ranges to earlier pieces of the same
+// long ranges (serving): a range that takes the bucket sieve resumes the
+// walks ws[i].src holds and stores its own end state in ws[i].dst; the
+// outputs ws[i].saved and ws[i].resumed say what it did.
 int run_job(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, const uint8_t *mode,
             const uint64_t *off, const uint64_t *cap, int elem_bytes, void *out, uint64_t *counts,
-            int32_t *status, hipStream_t stream, bool use_graph, bool async_ok = false)
+            int32_t *status, hipStream_t stream, bool use_graph, bool async_ok = false, WalkSpec *ws = nullptr)
 {
     Plan pl;
     int st = make_plan(c, n, lo, hi, mode, off, cap, elem_bytes, pl);
     if (st != SIEVE_OK)
         return st;
+    for (uint64_t i = 0; ws && i < n; ++i)
+        ws[i].saved = ws[i].resumed = 0;
     const uint64_t budget = c->bucket_budget;
-    if (pl.best <= budget)
+    if (pl.best <= budget) {
+        std::vector<WalkLink> links;
+        if (ws) {
+            links.assign(n, WalkLink{nullptr, nullptr, 0, 0});
+            for (uint64_t i = 0; i < n; ++i) {
+                const RangeDesc &d = pl.ranges[i];
+                if (d.kbig >= d.nact || d.ntiles >= 0x80000000u)
+                    continue;  // no bucket primes (or tiles past the states' reach)
+                const uint32_t nb = d.nact - d.kbig;
+                if (ws[i].src && ws[i].nsrc) {
+                    links[i].src = ws[i].src;
+                    links[i].nsrc = std::min(ws[i].nsrc, nb);
+                    ws[i].resumed = 1;
+                }
+                if (ws[i].dst && nb <= ws[i].dcap) {
+                    links[i].dst = ws[i].dst;
+                    ws[i].saved = nb;
+                }
+            }
+        }
         return run_job_once(c, n, lo, hi, mode, off, cap, elem_bytes, out, counts, status, stream, use_graph, pl,
-                            async_ok);
+                            async_ok, ws ? links.data() : nullptr);
+    }
     const uint64_t span = (uint64_t)kValsPerWord * (c->prm.segment_bytes / 8);
     std::vector<RangeDesc> d0 = pl.ranges;  // the whole ranges' plans
     std::vector<uint64_t> cur(lo, lo + n), acc(n, 0), tot(n, 0), per(n);
@@ -1315,9 +1354,9 @@ void plan_range(uint64_t lo, uint64_t hi, uint32_t pw, uint64_t &ntiles, uint64_
 }
 int run_job(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, const uint8_t *mode,
             const uint64_t *off, const uint64_t *cap, int elem_bytes, void *out, uint64_t *counts, int32_t *status,
-            hipStream_t stream, bool use_graph, bool async_ok)
+            hipStream_t stream, bool use_graph, bool async_ok, WalkSpec *ws)
 {
-    return ::run_job(c, n, lo, hi, mode, off, cap, elem_bytes, out, counts, status, stream, use_graph, async_ok);
+    return ::run_job(c, n, lo, hi, mode, off, cap, elem_bytes, out, counts, status, stream, use_graph, async_ok, ws);
 }
 int grow_base_primes(sieve_ctx *c, uint64_t limit) { return ::grow_base_primes(c, limit); }
 int ensure_capacity(sieve_ctx *c, uint64_t nranges, uint64_t nchunks, uint64_t ntiles, uint64_t gtiles)

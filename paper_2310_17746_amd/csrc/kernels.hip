@@ -844,7 +844,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W))) k_
 namespace {
 
 struct HitWalk {
-    uint32_t t1, b1, t5, b5;  // next hit (tile, bit) per plane; t = ntiles when done
+    uint32_t t1, b1, t5, b5;  // next hit (tile, bit) per plane; t >= the window's end when done
     uint32_t qp, rp;          // P div nbits, P mod nbits
     uint32_t c1, c5;          // residue mod 5 of the next hit's cofactor (5: not tracked)
 };
@@ -901,8 +901,10 @@ __device__ inline bool wide_first_hits(const BucketArgs &a, uint32_t P, uint64_t
     return true;
 }
 
-// First hits of prime k in tiles [w0, wend) of range d (tile indices
-// relative to the range's tile 0; t = wend when there is none).
+// First hits of prime k at or past tile w0 of range d, as tile indices
+// relative to the range's tile 0 (a first hit past wend keeps its true tile
+// on the 64-bit path; the wide path caps it at wend).  t = wend for a
+// prime that is not active there (k >= nact, or its square past wend).
 template <bool WIDE>
 __device__ inline HitWalk walk_init(const BucketArgs &a, const RangeDesc &d, uint32_t k, uint32_t w0,
                                     uint32_t wend)
@@ -974,12 +976,40 @@ __device__ inline HitWalk walk_init(const BucketArgs &a, const RangeDesc &d, uin
     }
     w.qp = pc.p / a.nbits;
     w.rp = pc.p - w.qp * a.nbits;
+    // The true tiles, also past wend: where a walk ends is kept for the
+    // range's next piece.
     const uint64_t t1 = tM + id1 / a.nbits, t5 = tM + id5 / a.nbits;
-    w.t1 = t1 < wend ? (uint32_t)t1 : wend;
+    w.t1 = t1 < 0xFFFFFFFFull ? (uint32_t)t1 : 0xFFFFFFFFu;
     w.b1 = id1 % a.nbits;
-    w.t5 = t5 < wend ? (uint32_t)t5 : wend;
+    w.t5 = t5 < 0xFFFFFFFFull ? (uint32_t)t5 : 0xFFFFFFFFu;
     w.b5 = id5 % a.nbits;
     return w;
+}
+
+// A walk resumed from the state a previous piece of the range left.
+__device__ inline HitWalk walk_resume(const WalkState &st, uint32_t P, uint32_t nbits)
+{
+    HitWalk w;
+    w.t1 = st.t1;
+    w.b1 = st.bc1 & 0x0FFFFFFFu;
+    w.c1 = st.bc1 >> 28;
+    w.t5 = st.t5;
+    w.b5 = st.bc5 & 0x0FFFFFFFu;
+    w.c5 = st.bc5 >> 28;
+    w.qp = P / nbits;
+    w.rp = P - w.qp * nbits;
+    return w;
+}
+
+// Where a finished walk goes on: the tiles relative to the one after wend.
+__device__ inline WalkState walk_state(const HitWalk &w, uint32_t wend)
+{
+    WalkState st;
+    st.t1 = w.t1 - wend;
+    st.bc1 = w.b1 | (w.c1 << 28);
+    st.t5 = w.t5 - wend;
+    st.bc5 = w.b5 | (w.c5 << 28);
+    return st;
 }
 
 // Range of unit u: the last range whose first unit is <= u.  Searches from
@@ -1040,7 +1070,11 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket(BucketArgs a)
         const uint32_t w0 = win * kBucketWindow;
         const uint32_t wend = (d.ntiles - w0) < kBucketWindow ? d.ntiles : w0 + kBucketWindow;
         const uint32_t k = d.kbig + blk * kBucketThreads + tid;
-        HitWalk w = walk_init<WIDE>(a, d, k, w0, wend);
+        // A range linked to its previous piece: the first window's walks of
+        // the primes that piece left a state for resume from it.
+        const WalkLink *link = (!WIDE && a.job->links != 0) ? &a.links[r] : nullptr;
+        const bool resume = link && w0 == 0 && link->src && k < d.nact && k - d.kbig < link->nsrc;
+        HitWalk w = resume ? walk_resume(link->src[k - d.kbig], a.prm[k].p, nbits) : walk_init<WIDE>(a, d, k, w0, wend);
 #ifdef SIEVE_MARK_COUNT
         // hits past the range's last plane word are binned but never applied
         const uint32_t lastbits = 32u * d.last_words;
@@ -1073,8 +1107,8 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket(BucketArgs a)
                     atomicAdd(&a.bcount[d.tile0 + w0 + i], s_cnt[i]);
         } else {
             uint32_t nk = 0;  // this thread's hits (the first kBucketKeep are kept)
+            HitWalk c = w;    // count first, without moving the walk
             {
-                HitWalk c = w;  // count first, without moving the walk
                 while (c.t1 < wend) {
 #ifdef SIEVE_MARK_COUNT
                     if (covered(c.t1, c.b1)) {
@@ -1106,6 +1140,9 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket(BucketArgs a)
                     walk_step(c.t5, c.b5, c.c5, c, nbits);
                 }
             }
+            // The range's last window: the walk's end state for the next piece.
+            if (link && link->dst && wend == d.ntiles && k < d.nact)
+                link->dst[k - d.kbig] = walk_state(c, wend);
             __syncthreads();
             for (uint32_t i = tid; i < wend - w0; i += kBucketThreads) {
                 const uint32_t n = s_cnt[i];

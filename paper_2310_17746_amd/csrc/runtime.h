@@ -185,6 +185,25 @@ int hip_status(hipError_t e);
 uint64_t isqrt_host(uint64_t n);
 // Tile plan of [lo, hi) for pw plane words per tile.
 void plan_range(uint64_t lo, uint64_t hi, uint32_t pw, uint64_t &ntiles, uint64_t &base, uint32_t &last_words);
+
+// Bucket walk state of one range of a job that continues an earlier piece of
+// the same long range, which ended at the tile where this one starts, in a
+// job with the same k_large.  src holds nsrc primes' states from k_large on
+// (the earlier piece's end state); dst (dcap entries) receives this range's
+// end state.  Device memory, owned by the caller; NULL / 0 for none.
+// run_job sets `saved` to the number of states it stored in dst and
+// `resumed` to 1 when the range's walks started from src (both 0 for a
+// range without bucket primes, a dst too small, or a job that had to be cut
+// into pieces itself).
+struct WalkSpec {
+    WalkState *src;
+    WalkState *dst;
+    uint32_t nsrc;
+    uint32_t dcap;
+    uint32_t saved;
+    uint32_t resumed;
+};
+
 // One job over n ranges (see api.hip) on `stream` (NULL: the context stream).
 // counts/status are host arrays of n entries (may be NULL).  List range i
 // writes its primes from element off[i] of `out`; `out` may be NULL, and
@@ -192,10 +211,11 @@ void plan_range(uint64_t lo, uint64_t hi, uint32_t pw, uint64_t &ntiles, uint64_
 // ranges of one job can write to unrelated buffers).  Synchronous
 // unless async_ok: then a job that needs no host decision mid-way returns
 // once enqueued, and counts/status are written when the stream reaches its
-// end.
+// end.  ws (n entries, or NULL): bucket walk state carried between the
+// pieces of long ranges (see WalkSpec).
 int run_job(sieve_ctx *c, uint64_t n, const uint64_t *lo, const uint64_t *hi, const uint8_t *mode,
             const uint64_t *off, const uint64_t *cap, int elem_bytes, void *out, uint64_t *counts, int32_t *status,
-            hipStream_t stream, bool use_graph, bool async_ok = false);
+            hipStream_t stream, bool use_graph, bool async_ok = false, WalkSpec *ws = nullptr);
 // Makes the resident base primes cover `limit`.
 int grow_base_primes(sieve_ctx *c, uint64_t limit);
 // Makes the job scratch hold a job of the given size (capacities only grow).

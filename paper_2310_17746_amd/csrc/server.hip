@@ -96,6 +96,13 @@ private:
     std::map<uint64_t, uint64_t> free_;
 };
 
+// Two device buffers of bucket walk state (one read, one written by a piece)
+// for one request at a time; pooled by the server.
+struct WalkBuf {
+    sieve::WalkState *p[2] = {nullptr, nullptr};
+    uint32_t cap = 0;  // states per buffer
+};
+
 struct Request {
     uint64_t tag = 0, lo = 0, hi = 0;
     int mode = 0;
@@ -113,6 +120,11 @@ struct Request {
     uint64_t off_bytes = 0, cap_elems = 0, arena_bytes = 0;
     bool has_arena = false;
     bool cancelled = false;
+    // Resident bucket walk state (a request cut into several pieces): the
+    // previous piece's end state is in wb->p[wcur] for wn primes from the
+    // bucket sieve's first prime wkl on; wn = 0: none.
+    WalkBuf *wb = nullptr;
+    uint32_t wcur = 0, wn = 0, wkl = 0;
 };
 
 struct Finished {
@@ -136,6 +148,7 @@ struct sieve_server {
     std::deque<sieve_completion> done;
     std::unordered_map<uint64_t, Request *> live;  // queued or active, by tag
     std::unordered_map<uint64_t, Finished> results;
+    std::vector<WalkBuf *> wfree, wall;  // walk-state buffers: free ones, all
     size_t rr = 0;
     bool stop = false;
     std::thread th;
@@ -165,6 +178,8 @@ void complete_locked(sieve_server *s, Request *r, int status, uint64_t t)
     c.mode = r->mode;
     s->done.push_back(c);
     s->live.erase(r->tag);
+    if (r->wb)
+        s->wfree.push_back(r->wb);
     if (r->has_arena) {
         if (status == SIEVE_OK && r->mode)
             s->results[r->tag] = Finished{r->off_bytes, r->arena_bytes, r->count};
@@ -182,6 +197,8 @@ struct Step {
     std::vector<uint8_t> mode;
     std::vector<int32_t> status;
     std::vector<std::pair<Request *, uint64_t>> pieces;  // request, tiles taken
+    std::vector<uint8_t> linked;  // piece continues its request's bucket walks
+    std::vector<sieve::rt::WalkSpec> ws;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool in_flight = false, timed = false;
     int rc = SIEVE_OK;
@@ -262,6 +279,48 @@ void finish_step(sieve_server *s, Step &st)
             st.rc = SIEVE_E_DEVICE;
     }
     apply_step(s, st);
+}
+
+// Walk-state buffers of at least `need` states per buffer for r: its own,
+// a free pooled pair, or a new one (NULL when the device has no memory).
+WalkBuf *walk_buffers(sieve_server *s, Request *r, uint32_t need)
+{
+    if (r->wb && r->wb->cap >= need)
+        return r->wb;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (r->wb) {
+            s->wfree.push_back(r->wb);  // too small: back to the pool
+            r->wb = nullptr;
+            r->wn = 0;
+        }
+        for (size_t i = 0; i < s->wfree.size(); ++i) {
+            if (s->wfree[i]->cap >= need) {
+                r->wb = s->wfree[i];
+                s->wfree.erase(s->wfree.begin() + i);
+                return r->wb;
+            }
+        }
+    }
+    WalkBuf *b = new (std::nothrow) WalkBuf();
+    if (!b)
+        return nullptr;
+    b->cap = need + need / 4;
+    for (auto &q : b->p) {
+        if (hipMalloc((void **)&q, (size_t)b->cap * sizeof(sieve::WalkState)) != hipSuccess) {
+            (void)hipGetLastError();
+            for (auto &x : b->p)
+                if (x)
+                    (void)hipFree(x);
+            delete b;
+            return nullptr;
+        }
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->wall.push_back(b);
+    s->st.walk_bytes += 2ull * b->cap * sizeof(sieve::WalkState);
+    r->wb = b;
+    return b;
 }
 
 void scheduler(sieve_server *s)
@@ -352,6 +411,7 @@ void scheduler(sieve_server *s)
                 st.cap.clear();
                 st.mode.clear();
                 st.pieces.clear();
+                st.linked.clear();
                 uint64_t budget = s->p.step_tiles;
                 const size_t n = s->active.size();
                 for (size_t k = 0; k < n && budget; ++k) {
@@ -374,6 +434,13 @@ void scheduler(sieve_server *s)
                     st.off.push_back(lst ? dst / eb + r->count : 0);
                     st.cap.push_back(lst ? r->cap_elems - r->count : 0);
                     st.pieces.emplace_back(r, take);
+                    // A request cut into pieces continues its bucket walks
+                    // from piece to piece when nothing of it is in flight
+                    // (else its chain of states starts over).
+                    const bool link = !s->p.restart_walks && take < r->ntiles && r->inflight == 0;
+                    st.linked.push_back(link ? 1 : 0);
+                    if (!link)
+                        r->wn = 0;
                     r->next_tile = k1;
                     r->inflight++;
                     r->issued++;
@@ -397,6 +464,32 @@ void scheduler(sieve_server *s)
         if (m) {
             st.counts.assign(m, 0);
             st.status.assign(m, 0);
+            // Walk links: a linked piece of a request whose ranges reach the
+            // bucket sieve reads its previous piece's end state and writes
+            // its own (none after the request's last piece).
+            bool any_link = false;
+            st.ws.assign(m, sieve::rt::WalkSpec{nullptr, nullptr, 0, 0, 0, 0});
+            for (uint64_t i = 0; i < m && st.rc == SIEVE_OK; ++i) {
+                Request *r = st.pieces[i].first;
+                if (!st.linked[i] || r->hi <= 4)
+                    continue;
+                const uint32_t nact = sieve::rt::primes_upto(c, sieve::rt::isqrt_host(r->hi - 1));
+                if (nact <= c->k_large)
+                    continue;  // no prime of the request reaches the bucket sieve
+                WalkBuf *b = walk_buffers(s, r, nact - c->k_large);
+                if (!b)
+                    continue;
+                sieve::rt::WalkSpec &w = st.ws[i];
+                if (r->wn && r->wkl == c->k_large) {
+                    w.src = b->p[r->wcur];
+                    w.nsrc = r->wn;
+                }
+                if (r->next_tile < r->ntiles) {
+                    w.dst = b->p[r->wcur ^ 1];
+                    w.dcap = b->cap;
+                }
+                any_link = true;
+            }
             const uint64_t bj = c->bucket_jobs;
             if (prev.in_flight) {
                 std::lock_guard<std::mutex> lk(s->mu);
@@ -407,8 +500,28 @@ void scheduler(sieve_server *s)
                 st.rc = sieve::rt::run_job(c, m, st.lo.data(), st.hi.data(), st.mode.data(), st.off.data(),
                                            st.cap.data(), (int)eb, nullptr, st.counts.data(),
                                            st.status.data(), c->stream, c->prm.use_graph != 0,
-                                           s->p.overlap != 0);
+                                           s->p.overlap != 0, any_link ? st.ws.data() : nullptr);
             st.buckets = c->bucket_jobs != bj;
+            // A job that ran the bucket sieve has finished when run_job
+            // returns: the states it stored become the next pieces' sources.
+            uint64_t resumed = 0;
+            for (uint64_t i = 0; i < m; ++i) {
+                if (!st.linked[i])
+                    continue;
+                Request *r = st.pieces[i].first;
+                if (st.rc == SIEVE_OK && st.ws[i].saved) {
+                    r->wcur ^= 1;
+                    r->wn = st.ws[i].saved;
+                    r->wkl = c->k_large;
+                } else {
+                    r->wn = 0;
+                }
+                resumed += st.rc == SIEVE_OK ? st.ws[i].resumed : 0u;
+            }
+            if (resumed) {
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->st.resumed_walks += resumed;
+            }
             st.timed = st.timed && hipEventRecord(st.ev1, c->stream) == hipSuccess;
             if (!st.timed)
                 (void)hipStreamSynchronize(c->stream);
@@ -659,6 +772,13 @@ int sieve_server_destroy(sieve_server *srv)
         delete r;
     for (Request *r : srv->active)
         delete r;
+    (void)hipSetDevice(srv->ctx->device);
+    for (WalkBuf *b : srv->wall) {
+        for (auto &q : b->p)
+            if (q)
+                (void)hipFree(q);
+        delete b;
+    }
     if (srv->arena_base) {
         (void)hipSetDevice(srv->ctx->device);
         (void)hipFree(srv->arena_base);

@@ -79,11 +79,33 @@ struct JobHeader {
     uint32_t nlist;      // list ranges
     void *out;           // caller's output buffer (list ranges)
     int32_t elem_bytes;  // 4 or 8
-    int32_t pad;
+    uint32_t links;      // 1: BucketArgs::links holds a walk link per range
     uint64_t nseg;       // scan segments over all list ranges
     uint64_t nvisit;     // sieve work units: strips (or tiles times their parts), over all ranges
     uint64_t gtiles;     // tiles of split ranges (global-bitmap slots)
     uint64_t gwords;     // words of those slots (2 planes each)
+};
+
+// Bucket walk state kept between consecutive pieces of one long range (a
+// serving request cut into steps): the pieces tile the range back to back,
+// so where a prime's walk ends past one piece is where it goes on in the
+// next (Sec. 2.4's incremental state, carried across jobs).  One WalkState
+// per prime k, at index k - kbig: the next hit of each plane as a tile
+// index relative to the piece that reads it, and the hit's bit | cofactor
+// residue mod 5 << 28 (5: not tracked).
+struct WalkState {
+    uint32_t t1, bc1, t5, bc5;
+};
+
+// Per range of a job (when JobHeader::links is 1): the walks of bucket
+// primes [kbig, kbig + nsrc) resume from src instead of a Table 1 start, and
+// the walks of every bucket prime [kbig, nact) store their end state in dst,
+// relative to the tile after the range's last.  Zero addresses: none.
+struct WalkLink {
+    WalkState *src;
+    WalkState *dst;
+    uint32_t nsrc;
+    uint32_t pad;
 };
 
 // The order in which the sieve kernel's workgroups take tiles: ranges in
@@ -166,6 +188,7 @@ struct BucketArgs {
     uint32_t win;                 // LDS bins per workgroup: >= the tiles of every unit's window
     uint32_t pad;
     unsigned long long *tally;    // debug build only, as in SieveArgs
+    const WalkLink *links;        // per range, read when JobHeader::links is 1
     // A window past 64 bits (range values are offsets from its base W):
     uint32_t wide;                // 1: starts from (W - 1) mod P, 64-bit Table 1
     uint32_t w5;                  // W mod 5

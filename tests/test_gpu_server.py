@@ -170,3 +170,44 @@ def test_submit_into_caller_buffers(sv, overlap):
         assert got[50]["status"] == 0
         assert np.array_equal(_u(srv.fetch(50, got[50]["count"])), want[0])
         assert got[100]["status"] == 0 and got[100]["count"] == 455052511
+
+
+@pytest.mark.parametrize("overlap", [0, 1])
+def test_resident_bucket_walks(overlap):
+    """Requests cut into many two-tile pieces whose large primes take the
+    bucket sieve: each piece resumes its request's bucket walks from the state
+    the previous piece left on the device (Sec. 2.4's incremental state) and
+    stores its own.  Counts and lists equal the oracle's and those of a server
+    that restarts every walk, and the resumed path ran."""
+    reqs = [(5 * 10 ** 13 + 7, 5 * 10 ** 13 + 73_000_000, 0),
+            (10 ** 14 - 30_000_000, 10 ** 14 + 12_000_000, 1),
+            (2 * 10 ** 13, 2 * 10 ** 13 + 50_000_001, 0),
+            (9 * 10 ** 13, 9 * 10 ** 13 + 10 ** 6, 1),
+            (7 * 10 ** 13 + 1, 7 * 10 ** 13 + 40_000_000, 1)]
+    want_c = [oracle.count(lo, hi) for lo, hi, _ in reqs]
+    want_l = {i: oracle.primes(lo, hi, elem_bytes=8) for i, (lo, hi, m) in enumerate(reqs) if m}
+    results = {}
+    with pkg.Sieve(0) as s:
+        s.base_primes(isqrt(max(hi for _, hi, _ in reqs)) + 1)
+        for restart in (0, 1):
+            print("resident walks: overlap %d restart %d" % (overlap, restart), flush=True)
+            with pkg.Server(s, step_tiles=8, quantum_tiles=2, overlap=overlap, restart_walks=restart,
+                            out_budget_bytes=256 << 20) as srv:
+                for i, (lo, hi, m) in enumerate(reqs):
+                    srv.submit(lo, hi, m, i)
+                got = _drain(srv, len(reqs))
+                lists = {i: _u(srv.fetch(i, got[i]["count"])) for i in want_l}
+                st = srv.stats()
+            for i in range(len(reqs)):
+                assert got[i]["status"] == 0 and got[i]["count"] == want_c[i], (restart, i, reqs[i])
+            for i, w in want_l.items():
+                assert np.array_equal(lists[i], w), (restart, i, reqs[i])
+            assert st["bucket_steps"] > 0
+            if restart:
+                assert st["resumed_walks"] == 0 and st["walk_bytes"] == 0
+            else:
+                assert st["walk_bytes"] > 0
+                if not overlap:
+                    assert st["resumed_walks"] > 20
+            results[restart] = ({i: got[i]["count"] for i in got}, lists)
+    assert results[0][0] == results[1][0]
