@@ -361,6 +361,9 @@ def bench_serve(pkg, workloads):
     # the same saturated run with step k + 1 enqueued while step k runs
     done_o, st_o, t0_o = run(np.zeros(n), overlap=1)
     mu_o = n / ((max(done_o[i]["t_done_ns"] for i in range(n)) - t0_o) * 1e-9)
+    # and with every piece restarting its bucket walks (no resident walk state)
+    done_r, st_r, t0_r = run(np.zeros(n), restart_walks=1)
+    mu_r = n / ((max(done_r[i]["t_done_ns"] for i in range(n)) - t0_r) * 1e-9)
     # every request finished, and the long job's count is pi(10^12)
     ok = all(done[i]["status"] == 0 for i in range(n + 1)) and int(done[n]["count"]) == PI_1E12
     span = (max(c["t_done_ns"] for c in done.values()) - t0) * 1e-9
@@ -371,6 +374,7 @@ def bench_serve(pkg, workloads):
                         "[2, 1e12] at t = 0", "ok": ok,
             "saturated_req_per_s": round(mu, 1), "lambda_req_per_s": round(lam, 1),
             "saturated_req_per_s_overlap": round(mu_o, 1),
+            "saturated_req_per_s_restart_walks": round(mu_r, 1),
             "p50_ms": round(float(np.percentile(lat, 50)), 3),
             "p99_ms": round(float(np.percentile(lat, 99)), 3),
             "mean_ms": round(float(lat.mean()), 3),
@@ -381,7 +385,11 @@ def bench_serve(pkg, workloads):
             # device time of the steps' jobs over the span from the first
             # arrival to the last completion
             "utilization": round(st["busy_ns"] / max(span * 1e9, 1), 4),
-            "steps": st["steps"], "overlap_steps": st["overlap_steps"]}
+            "steps": st["steps"], "overlap_steps": st["overlap_steps"],
+            # steps that ran the bucket sieve; pieces that resumed their
+            # request's walks from the device-resident state, and its memory
+            "bucket_steps": st["bucket_steps"], "resumed_walks": st["resumed_walks"],
+            "walk_state_bytes": st["walk_bytes"]}
 
 
 def bench_wide(pkg, torch, params, steps=3):
