@@ -172,13 +172,16 @@ def test_submit_into_caller_buffers(sv, overlap):
         assert got[100]["status"] == 0 and got[100]["count"] == 455052511
 
 
-@pytest.mark.parametrize("overlap", [0, 1])
-def test_resident_bucket_walks(overlap):
+@pytest.mark.parametrize("overlap,slices", [(0, 0), (1, 0), (0, "tiny"), (0, "exact")])
+def test_resident_bucket_walks(overlap, slices):
     """Requests cut into many two-tile pieces whose large primes take the
     bucket sieve: each piece resumes its request's bucket walks from the state
     the previous piece left on the device (Sec. 2.4's incremental state) and
     stores its own.  Counts and lists equal the oracle's and those of a server
-    that restarts every walk, and the resumed path ran."""
+    that restarts every walk, and the resumed path ran.  With one-entry
+    estimated slices every bucket job overflows and runs again in the exact
+    layout, after the estimated pass already stored the end state: the re-run
+    must resume from the same source."""
     reqs = [(5 * 10 ** 13 + 7, 5 * 10 ** 13 + 73_000_000, 0),
             (10 ** 14 - 30_000_000, 10 ** 14 + 12_000_000, 1),
             (2 * 10 ** 13, 2 * 10 ** 13 + 50_000_001, 0),
@@ -187,10 +190,11 @@ def test_resident_bucket_walks(overlap):
     want_c = [oracle.count(lo, hi) for lo, hi, _ in reqs]
     want_l = {i: oracle.primes(lo, hi, elem_bytes=8) for i, (lo, hi, m) in enumerate(reqs) if m}
     results = {}
-    with pkg.Sieve(0) as s:
+    prm = {0: {}, "tiny": dict(bucket_slices=pkg.BUCKET_TINY), "exact": dict(bucket_slices=pkg.BUCKET_EXACT)}[slices]
+    with pkg.Sieve(0, prm) as s:
         s.base_primes(isqrt(max(hi for _, hi, _ in reqs)) + 1)
         for restart in (0, 1):
-            print("resident walks: overlap %d restart %d" % (overlap, restart), flush=True)
+            print("resident walks: overlap %d slices %s restart %d" % (overlap, slices, restart), flush=True)
             with pkg.Server(s, step_tiles=8, quantum_tiles=2, overlap=overlap, restart_walks=restart,
                             out_budget_bytes=256 << 20) as srv:
                 for i, (lo, hi, m) in enumerate(reqs):
