@@ -361,9 +361,6 @@ def bench_serve(pkg, workloads):
     # the same saturated run with step k + 1 enqueued while step k runs
     done_o, st_o, t0_o = run(np.zeros(n), overlap=1)
     mu_o = n / ((max(done_o[i]["t_done_ns"] for i in range(n)) - t0_o) * 1e-9)
-    # and with every piece restarting its bucket walks (no resident walk state)
-    done_r, st_r, t0_r = run(np.zeros(n), restart_walks=1)
-    mu_r = n / ((max(done_r[i]["t_done_ns"] for i in range(n)) - t0_r) * 1e-9)
     # every request finished, and the long job's count is pi(10^12)
     ok = all(done[i]["status"] == 0 for i in range(n + 1)) and int(done[n]["count"]) == PI_1E12
     span = (max(c["t_done_ns"] for c in done.values()) - t0) * 1e-9
@@ -374,7 +371,6 @@ def bench_serve(pkg, workloads):
                         "[2, 1e12] at t = 0", "ok": ok,
             "saturated_req_per_s": round(mu, 1), "lambda_req_per_s": round(lam, 1),
             "saturated_req_per_s_overlap": round(mu_o, 1),
-            "saturated_req_per_s_restart_walks": round(mu_r, 1),
             "p50_ms": round(float(np.percentile(lat, 50)), 3),
             "p99_ms": round(float(np.percentile(lat, 99)), 3),
             "mean_ms": round(float(lat.mean()), 3),
@@ -390,6 +386,50 @@ def bench_serve(pkg, workloads):
             # request's walks from the device-resident state, and its memory
             "bucket_steps": st["bucket_steps"], "resumed_walks": st["resumed_walks"],
             "walk_state_bytes": st["walk_bytes"]}
+
+
+def bench_walks(pkg):
+    """Requests cut into many pieces that take the bucket sieve: 24 counts of
+    10^8 integers from lo log-uniform in [10^13, 10^14] (seed 3), two-tile
+    pieces.  Device time of the serving steps with each request's bucket walk
+    state kept on the device between pieces, against every piece restarting
+    its walks; the counts must agree."""
+    rng = np.random.default_rng(3)
+    n = 24
+    lo = np.floor(10 ** rng.uniform(13, 14, n)).astype(np.uint64)
+    hi = lo + np.uint64(10 ** 8)
+    s = pkg.Sieve(0)
+    s.ensure_base_for(int(hi.max()))
+    res = {}
+    for restart in (0, 1, 0, 1):  # the second run of each mode is kept
+        with pkg.Server(s, step_tiles=64, quantum_tiles=2, restart_walks=restart) as srv:
+            t0 = time.perf_counter()
+            for i in range(n):
+                srv.submit(int(lo[i]), int(hi[i]), 0, i)
+            done = {}
+            t_end = time.time() + 120
+            while len(done) < n:
+                if time.time() > t_end:
+                    raise RuntimeError("walk run did not finish")
+                for c in srv.poll(64, wait_ms=20):
+                    done[c["tag"]] = c
+            wall = time.perf_counter() - t0
+            st = srv.stats()
+        res[restart] = {"busy_ms": round(st["busy_ns"] * 1e-6, 3), "wall_ms": round(wall * 1e3, 3),
+                        "steps": st["steps"], "busy_ms_per_step": round(st["busy_ns"] * 1e-6 / max(st["steps"], 1), 4),
+                        "bucket_steps": st["bucket_steps"],
+                        "resumed_walks": st["resumed_walks"], "walk_state_bytes": st["walk_bytes"],
+                        "counts": [int(done[i]["count"]) for i in range(n)],
+                        "ok": all(done[i]["status"] == 0 for i in range(n))}
+    s.close()
+    ok = res[0]["ok"] and res[1]["ok"] and res[0]["counts"] == res[1]["counts"]
+    for r in res.values():
+        del r["counts"], r["ok"]
+    return {"workload": "24 counts of 10^8 integers from lo log-uniform [1e13, 1e14] (seed 3), served in "
+                        "two-tile pieces", "ok": ok, "resident_walks": res[0], "restarted_walks": res[1],
+            # (wall time includes the new server's allocation of the walk buffers)
+            "busy_per_step_ratio_resident_over_restarted":
+                round(res[0]["busy_ms_per_step"] / max(res[1]["busy_ms_per_step"], 1e-9), 3)}
 
 
 def bench_wide(pkg, torch, params, steps=3):
@@ -509,7 +549,7 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=10 ** 11,
                     help="integers of the oracle's timed slice (the top of the range)")
     ap.add_argument("--extra", default="",
-                    choices=["", "list_1e9", "list_window", "batch_4096", "serve_2000", "wide"],
+                    choices=["", "list_1e9", "list_window", "batch_4096", "serve_2000", "walks", "wide"],
                     help="run only this extra workload and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (5 times), the reference "
@@ -548,6 +588,7 @@ def main() -> int:
               "list_window": lambda: bench_list_window(pkg, torch, params),
               "batch_4096": lambda: bench_batch(pkg, torch, params, workloads),
               "serve_2000": lambda: bench_serve(pkg, workloads),
+              "walks": lambda: bench_walks(pkg),
               "wide": lambda: bench_wide(pkg, torch, params)}[args.extra]
         print(json.dumps({"extra": args.extra, **fn()}), flush=True)
         return 0
@@ -636,6 +677,7 @@ def main() -> int:
                          ("batch_4096", lambda: bench_batch(pkg, torch, bparams, workloads)),
                          ("stream", lambda: bench_stream(pkg, torch, params)),
                          ("serve_2000", lambda: bench_serve(pkg, workloads)),
+                         ("walks", lambda: bench_walks(pkg)),
                          ("wide", lambda: bench_wide(pkg, torch, params))):
             print("bench: %s" % name, file=sys.stderr, flush=True)
             extras[name] = fn()

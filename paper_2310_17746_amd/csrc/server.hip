@@ -97,7 +97,7 @@ private:
 };
 
 // Two device buffers of bucket walk state (one read, one written by a piece)
-// for one request at a time; pooled by the server.
+// for one request at a time, in one allocation; pooled by the server.
 struct WalkBuf {
     sieve::WalkState *p[2] = {nullptr, nullptr};
     uint32_t cap = 0;  // states per buffer
@@ -306,16 +306,12 @@ WalkBuf *walk_buffers(sieve_server *s, Request *r, uint32_t need)
     if (!b)
         return nullptr;
     b->cap = need + need / 4;
-    for (auto &q : b->p) {
-        if (hipMalloc((void **)&q, (size_t)b->cap * sizeof(sieve::WalkState)) != hipSuccess) {
-            (void)hipGetLastError();
-            for (auto &x : b->p)
-                if (x)
-                    (void)hipFree(x);
-            delete b;
-            return nullptr;
-        }
+    if (hipMalloc((void **)&b->p[0], 2 * (size_t)b->cap * sizeof(sieve::WalkState)) != hipSuccess) {
+        (void)hipGetLastError();
+        delete b;
+        return nullptr;
     }
+    b->p[1] = b->p[0] + b->cap;  // one allocation holds both buffers
     std::lock_guard<std::mutex> lk(s->mu);
     s->wall.push_back(b);
     s->st.walk_bytes += 2ull * b->cap * sizeof(sieve::WalkState);
@@ -774,9 +770,7 @@ int sieve_server_destroy(sieve_server *srv)
         delete r;
     (void)hipSetDevice(srv->ctx->device);
     for (WalkBuf *b : srv->wall) {
-        for (auto &q : b->p)
-            if (q)
-                (void)hipFree(q);
+        (void)hipFree(b->p[0]);
         delete b;
     }
     if (srv->arena_base) {
