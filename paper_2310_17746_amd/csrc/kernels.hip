@@ -859,7 +859,9 @@ __device__ inline void walk_step(uint32_t &t, uint32_t &b, uint32_t &c, const Hi
         b -= nbits;
         t += 1;
     }
-    c = c == 4 ? 0 : (c == 5 ? 5 : c + 1);
+    // c -> c + 1 mod 5, and 5 stays 5: a nibble table indexed by c, without
+    // branches (0..5 -> 1, 2, 3, 4, 0, 5)
+    c = (0x504321u >> (c << 2)) & 0xFu;
 }
 
 // Wide windows: the first hits of prime P (below 2^32) in plane order at or
@@ -1056,6 +1058,9 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket(BucketArgs a)
     const uint32_t nbits = a.nbits;
     MarkTally tally;
 
+    // Walk links (serving pieces of one long range), read once per launch.
+    const WalkLink *const links = (!WIDE && a.job->links != 0) ? a.links : nullptr;
+
     uint32_t r = 0;
     uint64_t r_end = 0;  // one past the last unit of range r
     for (uint64_t u = blockIdx.x; u < nunits; u += gridDim.x) {
@@ -1072,9 +1077,12 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket(BucketArgs a)
         const uint32_t k = d.kbig + blk * kBucketThreads + tid;
         // A range linked to its previous piece: the first window's walks of
         // the primes that piece left a state for resume from it.
-        const WalkLink *link = (!WIDE && a.job->links != 0) ? &a.links[r] : nullptr;
-        const bool resume = link && w0 == 0 && link->src && k < d.nact && k - d.kbig < link->nsrc;
-        HitWalk w = resume ? walk_resume(link->src[k - d.kbig], a.prm[k].p, nbits) : walk_init<WIDE>(a, d, k, w0, wend);
+        const WalkLink *const link = links ? &links[r] : nullptr;
+        HitWalk w;
+        if (link && w0 == 0 && link->src && k < d.nact && k - d.kbig < link->nsrc)
+            w = walk_resume(link->src[k - d.kbig], a.prm[k].p, nbits);
+        else
+            w = walk_init<WIDE>(a, d, k, w0, wend);
 #ifdef SIEVE_MARK_COUNT
         // hits past the range's last plane word are binned but never applied
         const uint32_t lastbits = 32u * d.last_words;
