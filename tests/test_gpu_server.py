@@ -172,7 +172,7 @@ def test_submit_into_caller_buffers(sv, overlap):
         assert got[100]["status"] == 0 and got[100]["count"] == 455052511
 
 
-@pytest.mark.parametrize("overlap,slices", [(0, 0), (1, 0), (0, "tiny"), (0, "exact")])
+@pytest.mark.parametrize("overlap,slices", [(0, 0), (1, 0), (0, "tiny"), (0, "exact"), (0, "s52"), (0, "s76")])
 def test_resident_bucket_walks(overlap, slices):
     """Requests cut into many two-tile pieces whose large primes take the
     bucket sieve: each piece resumes its request's bucket walks from the state
@@ -190,7 +190,10 @@ def test_resident_bucket_walks(overlap, slices):
     want_c = [oracle.count(lo, hi) for lo, hi, _ in reqs]
     want_l = {i: oracle.primes(lo, hi, elem_bytes=8) for i, (lo, hi, m) in enumerate(reqs) if m}
     results = {}
-    prm = {0: {}, "tiny": dict(bucket_slices=pkg.BUCKET_TINY), "exact": dict(bucket_slices=pkg.BUCKET_EXACT)}[slices]
+    prm = {0: {}, "tiny": dict(bucket_slices=pkg.BUCKET_TINY), "exact": dict(bucket_slices=pkg.BUCKET_EXACT),
+           # the autotuner's smaller tiles: more primes go through the bucket sieve
+           "s52": dict(segment_bytes=53248, block_threads=512, wg_per_cu=3),
+           "s76": dict(segment_bytes=77824, block_threads=512, wg_per_cu=2)}[slices]
     with pkg.Sieve(0, prm) as s:
         s.base_primes(isqrt(max(hi for _, hi, _ in reqs)) + 1)
         for restart in (0, 1):
